@@ -1,0 +1,140 @@
+"""Seeded synthetic LP generators shared by the oracle tests, the GPU tests and the bench.
+
+This module holds no arithmetic of the interior point method. It only draws
+inputs: a constraint matrix ``A`` (m x n, m << n, full row rank with
+probability 1), and a strictly feasible primal/dual pair from which the
+right-hand sides are built, so the LP
+
+    min c^T x  s.t.  A x = b, x >= 0          (primal, Section 1)
+    max b^T y  s.t.  A^T y + s = c, s >= 0     (dual, Section 1)
+
+is feasible and bounded by construction:
+
+    x0 ~ U(0.5, 1.5)^n,  b = A x0,
+    y0 ~ N(0, 1)^m,  s0 ~ U(0.5, 1.5)^n,  c = A^T y0 + s0.
+
+Draw order with ``numpy.random.default_rng(seed)``: A (pattern first for
+sparse A), then x0, y0, s0.
+
+The paper's own workloads are l1-SVM LPs on UCI data sets (Section 7,
+Table 1); those data sets are not used. The shapes here extend the paper's
+m << n regime; the values follow the recipe above.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+__all__ = ["LP", "dense_lp", "tiny_lp", "config", "bf16_round", "f32_round",
+           "CONFIGS"]
+
+
+@dataclass
+class LP:
+    """A standard-form LP ``min c^T x, A x = b, x >= 0`` plus its generator's witness pair."""
+    A: np.ndarray            # (m, n) float64 row-major (values may be bf16/fp32-representable)
+    b: np.ndarray            # (m,) float64
+    c: np.ndarray            # (n,) float64
+    x0: np.ndarray           # strictly feasible primal witness
+    y0: np.ndarray           # dual witness
+    s0: np.ndarray           # strictly positive dual slack witness
+    storage: str = "f64"     # element type the GPU path stores A in: "f64" | "f32" | "bf16"
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[1]
+
+
+def bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round float values to the nearest bfloat16 (ties to even); returned as float64.
+
+    Used so that the BF16-stored matrix *is* the problem: both precisions then
+    solve the same LP.
+    """
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    u = (u + np.uint64(0x7FFF) + lsb) >> np.uint64(16) << np.uint64(16)
+    return (u.astype(np.uint32).view(np.float32)).astype(np.float64)
+
+
+def f32_round(a: np.ndarray) -> np.ndarray:
+    """Round to the nearest float32; returned as float64."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _witness(rng: np.random.Generator, A: np.ndarray):
+    m, n = A.shape
+    x0 = rng.uniform(0.5, 1.5, size=n)
+    y0 = rng.standard_normal(m)
+    s0 = rng.uniform(0.5, 1.5, size=n)
+    b = A @ x0
+    c = A.T @ y0 + s0
+    return b, c, x0, y0, s0
+
+
+def dense_lp(m: int, n: int, seed: int = 0, storage: str = "f64", name: str = "") -> LP:
+    """Dense LP with A i.i.d. N(0, 1), rounded to ``storage`` precision."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n))
+    if storage == "bf16":
+        A = bf16_round(A)
+    elif storage == "f32":
+        A = f32_round(A)
+    b, c, x0, y0, s0 = _witness(rng, A)
+    return LP(A, b, c, x0, y0, s0, storage=storage, name=name or f"dense{m}x{n}s{seed}")
+
+
+def tiny_lp(m: int, n: int, seed: int) -> LP:
+    """Small dense LP for brute-force checks (same recipe as ``dense_lp``)."""
+    return dense_lp(m, n, seed, name=f"tiny{m}x{n}s{seed}")
+
+
+def illcond_lp(m: int, n: int, seed: int = 0, matrix_seed: int = 1000,
+               cond: float = 1e4, storage: str = "f32") -> LP:
+    """A = U diag(sigma) V^T with Haar U (m x m), V (n x m) orthonormal columns,
+    sigma log-spaced from 1 to ``cond``; A is drawn once from ``matrix_seed`` and
+    (b, c) from ``seed``."""
+    rng_a = np.random.default_rng(matrix_seed)
+    G = rng_a.standard_normal((m, m))
+    U, R = np.linalg.qr(G)
+    U = U * np.sign(np.diag(R))
+    H = rng_a.standard_normal((n, m))
+    V, R2 = np.linalg.qr(H)
+    V = V * np.sign(np.diag(R2))
+    sig = np.logspace(0.0, np.log10(cond), m)
+    A = (U * sig) @ V.T
+    A = f32_round(A) if storage == "f32" else (bf16_round(A) if storage == "bf16" else A)
+    rng = np.random.default_rng(seed)
+    b, c, x0, y0, s0 = _witness(rng, A)
+    return LP(A, b, c, x0, y0, s0, storage=storage, name=f"illcond{m}x{n}s{seed}")
+
+
+# Workload table: (m, n, storage, sketch width w, nonzeros per sketch row s, seeds)
+CONFIGS = {
+    0: dict(m=50, n=2000, storage="f64", w=200, s=1, seeds=[0]),
+    1: dict(m=500, n=100_000, storage="f64", w=2000, s=2, seeds=[0, 1, 2, 3, 4]),
+    3: dict(m=2000, n=200_000, storage="f32", w=8000, s=2, seeds=list(range(80))),
+    "4d": dict(m=2000, n=2_000_000, storage="bf16", w=16000, s=2, seeds=[0]),
+}
+
+
+def config(i, seed: Optional[int] = None) -> LP:
+    """Build workload ``i`` (0, 1, 3 or "4d") at ``seed`` (defaults to its first seed)."""
+    cfg = CONFIGS[i]
+    sd = cfg["seeds"][0] if seed is None else seed
+    if i == 3:
+        lp = illcond_lp(cfg["m"], cfg["n"], seed=sd, storage=cfg["storage"])
+    else:
+        lp = dense_lp(cfg["m"], cfg["n"], seed=sd, storage=cfg["storage"],
+                      name=f"cfg{i}s{sd}")
+    lp.meta.update(w=cfg["w"], s=cfg["s"], config=i, seed=sd)
+    return lp

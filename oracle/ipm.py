@@ -1,0 +1,415 @@
+"""Infeasible long-step IPM with a sketch-preconditioned CG normal-equations solve.
+
+TEST INFRASTRUCTURE (oracle). Plain FP64 NumPy/SciPy, written from the paper:
+
+* LP and dual (Section 1, eqs. primal and dual); normal equations
+  A D^2 A^T dy = p with D = X^{1/2} S^{-1/2} (Section 1, eq. normal).
+* Residuals r_p = A x - b, r_d = A^T y + s - c (Section 5, eq. ipm_residuals).
+* Right-hand side p = -r_p - sigma mu A S^{-1} 1 + A x - A D^2 r_d (Section 5,
+  below eq. ipm_inf). -r_p + A x equals b, so it is evaluated as
+  p = b - A (sigma mu / s + d^2 * r_d); a test checks the two forms agree.
+* Algorithm 1 (Section 3): B = A D W, Q = B B^T (eqn. pdprecond), CG on the
+  preconditioned system (eq. precond_alt). Q^{-1/2} from the SVD of B and a
+  Cholesky factor L of Q give the same CG iterates, and the paper's residual
+  norm ||Q^{-1/2} r|| equals ||L^{-1} r||, so Cholesky replaces the SVD.
+  Stopping: ||L^{-1} r_j|| <= tol * ||L^{-1} p|| (eq. pdcond2 with a tolerance
+  in place of the fixed iteration count t).
+* Perturbation v = (XS)^{1/2} W (ADW)^+ (A D^2 A^T dy - p) (Section 4,
+  eq. compv) with (ADW)^+ = B^T Q^{-1} since B has full row rank (Lemma
+  fullrankR). The residual is the true one, recomputed from dy.
+* Directions (Section 5, eq. ipm_inf): ds = -r_d - A^T dy,
+  dx = -x + sigma mu / s - d^2 * ds - v / s.
+* Step lengths (Algorithm 3, steps 6-7): alpha_max is the end of the
+  connected segment [0, alpha] that stays in the infeasible neighbourhood
+  N(gamma) = {x_i s_i >= (1-gamma) mu, ||r|| / ||r0|| <= mu / mu0} (Section 5),
+  with a backoff theta when it is below 1; alpha_bar minimises mu(alpha) on
+  [0, alpha_max]. Update (Algorithm 3, step 8).
+
+Where the paper is silent the following readings apply (both the oracle and
+the GPU library implement them): gamma = 0.9, sigma = 0.5, theta = 0.9999;
+the neighbourhood's residual term uses the exact contraction r(alpha) =
+(1 - alpha) r that the perturbation v guarantees; a constraint already
+violated by rounding at alpha = 0 is only kept from getting worse; the stop
+test is relative gap, primal and dual residual all <= gap_tol; CG stops early
+when its preconditioned residual drops by less than 1 % over 10 iterations.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import Callable, Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+from .sketch import sketch_ADW, sketch_matrix
+
+# status values (oracle-side names)
+OK = 0
+CONVERGED = 1
+PCG_MAXIT = 2
+PCG_STAGNATED = 3
+ERR_NOT_SPD = -3
+ERR_BREAKDOWN = -4
+ERR_STALL = -5
+
+
+@dataclass
+class Params:
+    sigma: float = 0.5
+    gamma: float = 0.9
+    theta: float = 0.9999
+    tol_pcg: float = 1e-10
+    maxit_pcg: int = 500
+    gap_tol: float = 1e-8
+    maxit_ipm: int = 200
+    w: int = 0
+    s: int = 2
+    seed: int = 0
+    vcorr: bool = True
+    stag_window: int = 10
+    stag_ratio: float = 0.99
+    min_step: float = 1e-14
+    max_redraws: int = 3
+
+
+@dataclass
+class State:
+    x: np.ndarray
+    y: np.ndarray
+    s: np.ndarray
+    k: int = 0
+    mu0: float = 0.0
+    r0norm: float = 0.0
+
+
+@dataclass
+class StepInfo:
+    status: int = OK
+    k: int = 0
+    mu: float = 0.0
+    gap: float = 0.0
+    relgap: float = 0.0
+    rp_rel: float = 0.0
+    rd_rel: float = 0.0
+    obj: float = 0.0
+    alpha_max: float = 0.0
+    alpha: float = 0.0
+    pcg_iters: int = 0
+    pcg_status: int = OK
+    pcg_relres: float = 0.0
+    vnorm: float = 0.0
+    extra: dict = field(default_factory=dict)
+
+
+def initial_state(A: np.ndarray, b: np.ndarray, c: np.ndarray) -> State:
+    """x = s = 1, y = 0; mu0 and ||r0|| taken at this point (start of Algorithm 3)."""
+    m, n = A.shape
+    st = State(np.ones(n), np.zeros(m), np.ones(n), 0)
+    rp, rd = residuals(A, b, c, st.x, st.y, st.s)
+    st.mu0 = float(st.x @ st.s / n)
+    st.r0norm = float(np.sqrt(rp @ rp + rd @ rd))
+    return st
+
+
+def residuals(A, b, c, x, y, s):
+    """Primal and dual residuals (Section 5, eq. ipm_residuals); r_p in R^m, r_d in R^n."""
+    return A @ x - b, A.T @ y + s - c
+
+
+def rhs_p(A, b, x, s, rd, sigma, mu):
+    """p = b - A (sigma mu / s + d^2 r_d), the infeasible right-hand side of Section 5."""
+    return b - A @ (sigma * mu / s + (x / s) * rd)
+
+
+def rhs_p_paper_form(A, b, x, s, rd, sigma, mu):
+    """p = -r_p - sigma mu A S^{-1} 1 + A x - A D^2 r_d exactly as printed (Section 5)."""
+    rp = A @ x - b
+    return -rp - sigma * mu * (A @ (1.0 / s)) + A @ x - A @ ((x / s) * rd)
+
+
+def stop_metrics(A, b, c, x, y, s, rp, rd):
+    """Duality gap and relative residuals used by the stop test."""
+    ctx = float(c @ x)
+    gap = ctx - float(b @ y)
+    return dict(
+        gap=gap,
+        relgap=abs(gap) / (1.0 + abs(ctx)),
+        rp_rel=float(np.linalg.norm(rp)) / (1.0 + float(np.linalg.norm(b))),
+        rd_rel=float(np.linalg.norm(rd)) / (1.0 + float(np.linalg.norm(c))),
+        obj=ctx,
+    )
+
+
+# ---------------------------------------------------------------- PCG (Algorithm 1)
+
+@dataclass
+class PCGResult:
+    dy: np.ndarray
+    iters: int
+    status: int
+    relres: float            # ||L^{-1} r|| / ||L^{-1} p|| at exit (recursive residual)
+    history: list            # ||L^{-1} r_j|| for j = 0..iters
+    rho_star: float          # ||L^{-1} p||^2
+    warm_used: bool = False
+
+
+def pcg(matvec: Callable, L: np.ndarray, p: np.ndarray, tol: float, maxit: int,
+        dy0: Optional[np.ndarray] = None, stag_window: int = 10,
+        stag_ratio: float = 0.99) -> PCGResult:
+    """CG on Q^{-1/2} M Q^{-1/2} z = Q^{-1/2} p written with the preconditioner Q = L L^T.
+
+    ``matvec(v)`` applies M = A D^2 A^T. The residual norm reported is the
+    paper's ||f|| = ||Q^{-1/2}(M dy - p)|| = ||L^{-1} r|| (Section 3.1).
+    A warm start dy0 is used only if its residual is smaller than that of 0.
+    """
+    def lsolve(r):
+        return sla.solve_triangular(L, r, lower=True)
+
+    def ltsolve(wv):
+        return sla.solve_triangular(L, wv, lower=True, trans="T")
+
+    m = p.shape[0]
+    wp = lsolve(p)
+    rho_star = float(wp @ wp)
+    dy = np.zeros(m)
+    r = p.copy()
+    wv = wp
+    warm_used = False
+    if dy0 is not None:
+        r0 = p - matvec(dy0)
+        w0 = lsolve(r0)
+        if float(w0 @ w0) < rho_star:
+            dy, r, wv, warm_used = dy0.copy(), r0, w0, True
+    rho = float(wv @ wv)
+    hist = [np.sqrt(rho)]
+    thresh = tol * np.sqrt(rho_star)
+    if np.sqrt(rho) <= thresh:
+        rel = np.sqrt(rho / rho_star) if rho_star > 0 else 0.0
+        return PCGResult(dy, 0, OK, rel, hist, rho_star, warm_used)
+    z = ltsolve(wv)
+    d = z.copy()
+    status = PCG_MAXIT
+    it = 0
+    while it < maxit:
+        q = matvec(d)
+        dq = float(d @ q)
+        if not dq > 0.0:
+            status = ERR_BREAKDOWN
+            break
+        alpha = rho / dq
+        dy = dy + alpha * d
+        r = r - alpha * q
+        wv = lsolve(r)
+        rho_new = float(wv @ wv)
+        it += 1
+        hist.append(np.sqrt(rho_new))
+        if np.sqrt(rho_new) <= thresh:
+            status = OK
+            break
+        if it >= stag_window and hist[-1] > stag_ratio * hist[-1 - stag_window]:
+            status = PCG_STAGNATED
+            break
+        z = ltsolve(wv)
+        d = z + (rho_new / rho) * d
+        rho = rho_new
+    return PCGResult(dy, it, status, hist[-1] / np.sqrt(rho_star), hist, rho_star, warm_used)
+
+
+# ---------------------------------------------------------------- step lengths
+
+def first_exit(cq, bq, aq):
+    """Smallest alpha > 0 at which cq + bq*alpha + aq*alpha^2 drops below min(cq, 0).
+
+    Vectorised over arrays; returns +inf where that never happens. A constraint
+    already violated at 0 by rounding (cq < 0) is measured against its value
+    at 0, i.e. cq is taken as 0 after shifting.
+    """
+    cq = np.maximum(np.asarray(cq, dtype=np.float64), 0.0)
+    bq = np.asarray(bq, dtype=np.float64)
+    aq = np.asarray(aq, dtype=np.float64)
+    cq, bq, aq = np.broadcast_arrays(cq, bq, aq)
+    out = np.full(cq.shape, np.inf)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        # c == 0: alpha*(b + a alpha)
+        z = cq == 0.0
+        zneg = z & ((bq < 0) | ((bq == 0) & (aq < 0)))
+        out[zneg] = 0.0
+        zpos = z & ~zneg & (aq < 0)
+        out[zpos] = -bq[zpos] / aq[zpos]
+        # c > 0, linear
+        lin = (~z) & (aq == 0.0) & (bq < 0)
+        out[lin] = -cq[lin] / bq[lin]
+        # c > 0, quadratic
+        qd = (~z) & (aq != 0.0)
+        disc = bq * bq - 4.0 * aq * cq
+        ok = qd & (disc >= 0)
+        sq = np.sqrt(np.where(ok, disc, 0.0))
+        qq = -0.5 * (bq + np.copysign(sq, bq))
+        r1 = np.where(ok, qq / aq, np.inf)
+        r2 = np.where(ok & (qq != 0), cq / qq, np.inf)
+        r1 = np.where(r1 > 0, r1, np.inf)
+        r2 = np.where(r2 > 0, r2, np.inf)
+        out[qd] = np.minimum(r1, r2)[qd]
+    return out
+
+
+def step_lengths(x, s, dx, ds, gamma, theta, mu0, r0norm, rnorm):
+    """alpha_max and alpha_bar of Algorithm 3, steps 6-7 (closed form).
+
+    mu(alpha) = (x^T s + alpha a1 + alpha^2 a2) / n with a1 = x^T ds + s^T dx,
+    a2 = dx^T ds; x_i(alpha) s_i(alpha) = x_i s_i + alpha (x_i ds_i + s_i dx_i)
+    + alpha^2 dx_i ds_i.
+    """
+    n = x.shape[0]
+    xs = float(x @ s)
+    a1 = float(x @ ds + s @ dx)
+    a2 = float(dx @ ds)
+    mu = xs / n
+    g = 1.0 - gamma
+    roots = [
+        first_exit(x * s - g * mu, x * ds + s * dx - g * a1 / n, dx * ds - g * a2 / n).min(),
+        first_exit(x, dx, 0.0).min(),
+        first_exit(s, ds, 0.0).min(),
+    ]
+    if r0norm > 0:
+        rho = rnorm / r0norm
+        roots.append(float(first_exit(xs / (n * mu0) - rho, a1 / (n * mu0) + rho, a2 / (n * mu0))))
+    amax = min(1.0, min(roots))
+    if amax < 1.0:
+        amax *= theta
+    if a2 > 0:
+        abar = min(max(-a1 / (2.0 * a2), 0.0), amax)
+    else:
+        abar = amax if (a1 * amax + a2 * amax * amax) <= 0.0 else 0.0
+    return amax, abar, dict(a1=a1, a2=a2)
+
+
+# ---------------------------------------------------------------- sketch redraws
+
+def sketch_size(w: int, s: int, attempt: int):
+    """(w, s) of redraw ``attempt``: w doubles per redraw, s is at least 2 after the first."""
+    if attempt == 0:
+        return w, s
+    return w << attempt, max(s, 2)
+
+
+def sketch_seed(seed: int, attempt: int) -> int:
+    """Seed of redraw ``attempt``; the first draw uses the caller's seed unchanged."""
+    return seed if attempt == 0 else (seed + attempt * 0x632BE59BD9B4E019) & ((1 << 64) - 1)
+
+
+# ---------------------------------------------------------------- one IPM iteration
+
+def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
+         keep: bool = False) -> tuple:
+    """One iteration of Algorithm 3 from state ``st``; returns (new_state, StepInfo).
+
+    mode "exact": A D^2 A^T dy = p solved by Cholesky, v = 0 (IPM with a direct
+    solver). mode "sketch": Algorithm 1 with the hash sketch of oracle.sketch and
+    the perturbation v of eq. compv (v = 0 if prm.vcorr is False).
+    If the stop test already holds, the state is returned unchanged with
+    status CONVERGED.
+    """
+    x, y, s = st.x, st.y, st.s
+    m, n = A.shape
+    mu = float(x @ s) / n
+    rp, rd = residuals(A, b, c, x, y, s)
+    met = stop_metrics(A, b, c, x, y, s, rp, rd)
+    info = StepInfo(k=st.k, mu=mu, gap=met["gap"], relgap=met["relgap"],
+                    rp_rel=met["rp_rel"], rd_rel=met["rd_rel"], obj=met["obj"])
+    if max(met["relgap"], met["rp_rel"], met["rd_rel"]) <= prm.gap_tol:
+        info.status = CONVERGED
+        return st, info
+    d2 = x / s
+    p = rhs_p(A, b, x, s, rd, prm.sigma, mu)
+
+    def matvec(v):
+        return A @ (d2 * (A.T @ v))
+
+    v = np.zeros(n)
+    if mode == "exact":
+        Mmat = (A * d2) @ A.T
+        try:
+            L = sla.cholesky(Mmat, lower=True)
+        except np.linalg.LinAlgError:
+            info.status = ERR_NOT_SPD
+            return st, info
+        dy = sla.cho_solve((L, True), p)
+    else:
+        res = None
+        for attempt in range(prm.max_redraws + 1):
+            w, sk = sketch_size(prm.w, prm.s, attempt)
+            key = sketch_seed(prm.seed, attempt)
+            B = sketch_ADW(A, np.sqrt(d2), w, sk, key, st.k)
+            Q = B @ B.T
+            try:
+                L = sla.cholesky(Q, lower=True)
+            except np.linalg.LinAlgError:
+                info.status = ERR_NOT_SPD
+                continue
+            res = pcg(matvec, L, p, prm.tol_pcg, prm.maxit_pcg, dy0=dy0,
+                      stag_window=prm.stag_window, stag_ratio=prm.stag_ratio)
+            info.status = OK
+            if res.status == OK:
+                break
+        info.extra.update(attempts=attempt + 1, w_used=w, s_used=sk)
+        if res is None:
+            return st, info
+        info.pcg_iters, info.pcg_status, info.pcg_relres = res.iters, res.status, res.relres
+        if res.status == ERR_BREAKDOWN:
+            info.status = ERR_BREAKDOWN
+            return st, info
+        dy = res.dy
+        if prm.vcorr:
+            rhat = matvec(dy) - p
+            gq = sla.cho_solve((L, True), rhat)
+            u = B.T @ gq
+            W = sketch_matrix(n, w, sk, key, st.k)
+            v = np.sqrt(x * s) * (W @ u)
+        if keep:
+            info.extra.update(B=B, Q=Q, L=L, pcg=res)
+    ds = -rd - A.T @ dy
+    dx = -x + prm.sigma * mu / s - d2 * ds - v / s
+    rnorm = float(np.sqrt(rp @ rp + rd @ rd))
+    amax, abar, aux = step_lengths(x, s, dx, ds, prm.gamma, prm.theta, st.mu0, st.r0norm, rnorm)
+    info.alpha_max, info.alpha = amax, abar
+    info.vnorm = float(np.linalg.norm(v))
+    if keep:
+        info.extra.update(p=p, dy=dy, dx=dx, ds=ds, v=v, d2=d2, rp=rp, rd=rd, **aux)
+    if abar < prm.min_step:
+        info.status = ERR_STALL
+        return st, info
+    new = State(x + abar * dx, y + abar * dy, s + abar * ds, st.k + 1, st.mu0, st.r0norm)
+    if info.status == OK and mode != "exact":
+        info.status = info.pcg_status if info.pcg_status > 0 else OK
+    return new, info
+
+
+@dataclass
+class SolveResult:
+    state: State
+    infos: list
+    converged: bool
+    status: int
+
+
+def solve(A, b, c, prm: Params, mode: str = "sketch", st: Optional[State] = None,
+          callback=None) -> SolveResult:
+    """Run Algorithm 3 from x = s = 1, y = 0 until the stop test holds or maxit_ipm."""
+    st = initial_state(A, b, c) if st is None else st
+    infos = []
+    for _ in range(prm.maxit_ipm + 1):
+        new, info = step(A, b, c, st, prm, mode)
+        infos.append(info)
+        if callback is not None:
+            callback(st, info)
+        if info.status == CONVERGED:
+            return SolveResult(st, infos, True, CONVERGED)
+        if info.status < 0:
+            return SolveResult(st, infos, False, info.status)
+        st = new
+    return SolveResult(st, infos, False, OK)
+
+
+def with_params(prm: Params, **kw) -> Params:
+    return replace(prm, **kw)
