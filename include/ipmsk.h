@@ -1,0 +1,211 @@
+/*
+ * ipmsk.h - C ABI of the sketch-preconditioned interior point hot path for MI355X (gfx950).
+ *
+ * The library computes, on one GPU, the pieces of one iteration of the infeasible long-step
+ * interior point method of Chowdhury, Dexter, London, Avron and Drineas ("Faster Randomized
+ * Interior Point Methods for Tall/Wide Linear Programs"):
+ *
+ *   LP      min c^T x  s.t.  A x = b, x >= 0;   dual  max b^T y  s.t.  A^T y + s = c, s >= 0
+ *           (Section 1, eqs. primal and dual), A is m x n with m << n and rank m.
+ *   Normal  A D^2 A^T dy = p,  D = X^{1/2} S^{-1/2}  (Section 1, eq. normal).
+ *   Solve   Algorithm 1 (Section 3): sketch B = A D W, preconditioner Q = B B^T
+ *           (eqn. pdprecond), conjugate gradients on the preconditioned system
+ *           (eq. precond_alt). Q is factored by Cholesky (Q = L L^T) instead of the SVD; the
+ *           CG iterates and the residual norm ||Q^{-1/2} r|| = ||L^{-1} r|| are the same.
+ *   Step    Algorithm 3 (Section 5) with the perturbation v of eq. compv.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked [device] are device pointers on the context's device, owned by the
+ *     caller; the library never frees them and never keeps them after the call returns.
+ *   - All work is ordered on the context's stream. Entry points that return scalar results
+ *     (info structs, bad_pivot) synchronize that stream before returning; the others may return
+ *     before the device work finishes.
+ *   - Return value: IPM_OK (0), a warning (> 0) or an error (< 0). Arguments are validated
+ *     before any device work is queued; on an error a message is available from
+ *     ipm_last_error(). No C++ exception crosses this interface.
+ *   - Dense matrices are row-major: element (i, j) of an m x n matrix with row stride ld is at
+ *     offset i*ld + j. For the dense A of ipm_matrix, ld must be a multiple of 16/elem_size and
+ *     the base pointer 16-byte aligned (the HBM passes use 16-byte vector loads); columns
+ *     n..ld-1 are never read.
+ *   - One context per host thread. Calls on one context must not overlap.
+ */
+#ifndef IPMSK_H
+#define IPMSK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------------- */
+#define IPM_OK              0
+#define IPM_CONVERGED       1   /* ipm_step: the stop test already holds; no step was taken   */
+#define IPM_PCG_MAXIT       2   /* warning: CG reached maxit_pcg before the tolerance         */
+#define IPM_PCG_STAGNATED   3   /* warning: CG residual fell by < stag_ratio over stag_window */
+#define IPM_ERR_ARG        -1   /* invalid argument (null pointer, bad size, s not dividing w) */
+#define IPM_ERR_HIP        -2   /* HIP runtime failure                                       */
+#define IPM_ERR_NOT_SPD    -3   /* Cholesky of Q met a non-positive pivot                     */
+#define IPM_ERR_BREAKDOWN  -4   /* CG met d^T A D^2 A^T d <= 0                                */
+#define IPM_ERR_STALL      -5   /* step length below min_step                                 */
+#define IPM_ERR_NOMEM      -6   /* workspace allocation failed                                */
+
+/* ---- element types and layouts ------------------------------------------------------------ */
+#define IPM_F64   0
+#define IPM_F32   1
+#define IPM_BF16  2
+#define IPM_DENSE_ROWMAJOR 0
+
+typedef struct ipm_ctx ipm_ctx;
+
+/* Constraint matrix A (m x n). val [device]: m*ld elements of `dtype`. */
+typedef struct {
+    int64_t m, n, ld;
+    int32_t layout;          /* IPM_DENSE_ROWMAJOR */
+    int32_t dtype;           /* IPM_F64 | IPM_F32 | IPM_BF16 */
+    const void* val;
+} ipm_matrix;
+
+/* LP data: b [device] m doubles, c [device] n doubles. */
+typedef struct {
+    ipm_matrix A;
+    const double* b;
+    const double* c;
+} ipm_problem;
+
+/* Iterate (x, y, s) [device, n / m / n doubles, updated in place], iteration counter k, and
+ * the neighbourhood's reference values mu0 = x0^T s0 / n and ||r0|| = ||(r_p0, r_d0)||
+ * (Section 5). If r0norm < 0 the first ipm_step sets mu0 and r0norm from the current point. */
+typedef struct {
+    double* x;
+    double* y;
+    double* s;
+    int64_t k;
+    double mu0;
+    double r0norm;
+} ipm_state;
+
+/* Method parameters. ipm_params_default() fills the values used throughout:
+ * sigma 0.5 (Section 7), gamma 0.9, theta 0.9999, tol_pcg 1e-10, gap_tol 1e-8,
+ * min_step 1e-14, maxit_pcg 500, stag_window 10, stag_ratio 0.99, max_redraws 3, vcorr 1. */
+typedef struct {
+    double sigma;        /* centering parameter, in (0, 4/5) (Algorithm 3 input)            */
+    double gamma;        /* neighbourhood parameter, in (0, 1)                              */
+    double theta;        /* backoff applied to alpha_max when alpha_max < 1                 */
+    double tol_pcg;      /* CG stops when ||L^-1 r|| <= tol_pcg ||L^-1 p|| (eq. pdcond2)   */
+    double gap_tol;      /* stop test: relative gap and both relative residuals <= gap_tol  */
+    double min_step;     /* alpha_bar below this is IPM_ERR_STALL                            */
+    double stag_ratio;   /* CG stagnation: residual > stag_ratio * residual stag_window ago */
+    int32_t w;           /* sketch width (columns of W); s must divide w; w >= m           */
+    int32_t s;           /* nonzeros per row of W, 1..8                                     */
+    int32_t maxit_pcg;
+    int32_t stag_window;
+    int32_t max_redraws; /* extra draws of W (doubled w, s >= 2) after a failed solve      */
+    int32_t vcorr;       /* 1: perturbation v of eq. compv; 0: v = 0                         */
+    uint64_t seed;       /* sketch seed                                                     */
+} ipm_params;
+
+typedef struct {
+    int32_t iters;       /* CG iterations performed                                         */
+    int32_t status;      /* IPM_OK, IPM_PCG_MAXIT, IPM_PCG_STAGNATED or IPM_ERR_BREAKDOWN    */
+    int32_t warm_used;   /* 1 if the initial dy was kept (its residual beat dy = 0)          */
+    int32_t reserved;
+    double relres;       /* ||L^-1 r|| / ||L^-1 p|| at exit (recursive residual)             */
+    double rho_star;     /* ||L^-1 p||^2                                                     */
+} ipm_pcg_info;
+
+typedef struct {
+    int32_t status;      /* IPM_OK, IPM_CONVERGED, warnings, or an error                    */
+    int32_t pcg_status;
+    int32_t pcg_iters;   /* CG iterations of the accepted draw                              */
+    int32_t attempts;    /* draws of W used (1 + redraws)                                   */
+    int64_t k;           /* iteration index of the point this info describes                */
+    int32_t w_used, s_used;
+    double mu, gap, relgap, rp_rel, rd_rel, obj;   /* at the point before the step          */
+    double alpha_max, alpha;                       /* Algorithm 3, steps 6-7                 */
+    double pcg_relres, vnorm;
+} ipm_step_info;
+
+/* ---- context ------------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` that orders its work on `hip_stream` (a hipStream_t;
+ * NULL = the default stream). The context owns its workspace (grown on demand, freed by
+ * ipm_ctx_destroy). Returns IPM_ERR_HIP if the device cannot be used. */
+int  ipm_ctx_create(ipm_ctx** out, int device, void* hip_stream);
+void ipm_ctx_destroy(ipm_ctx* ctx);
+int  ipm_ctx_set_stream(ipm_ctx* ctx, void* hip_stream);
+const char* ipm_last_error(const ipm_ctx* ctx);
+void ipm_params_default(ipm_params* p);
+
+/* ---- the hot path ----------------------------------------------------------------------- */
+
+/* Sketch B = A diag(d) W (Algorithm 1, step 1; Section 2's sparse embedding).
+ * W is the n x w matrix with exactly s nonzeros per row: row j, copy r (0 <= r < s) sits in
+ * bucket r*(w/s) + floor(hi32(h) * (w/s) / 2^32) with value +1/sqrt(s) if bit 0 of h is 0,
+ * else -1/sqrt(s), where h = mix64(K + (j+1)*phi), K = mix64((seed ^ mix64(k)) + (r+1)*phi),
+ * phi = 0x9E3779B97F4A7C15 and mix64 is the SplitMix64 output function (Steele, Lea, Flood
+ * 2014). k is the IPM iteration (W is redrawn every iteration, Algorithm 3 step 2).
+ *   A    dense m x n, any dtype;  d [device] n doubles (the diagonal of D)
+ *   B    [device] m x w row-major, out_dtype IPM_F64 or IPM_F32; overwritten.
+ * Errors: IPM_ERR_ARG if w < 1, s < 1, s > 8, s does not divide w, or pointers are null. */
+int ipm_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* d, uint64_t seed, int64_t k,
+               int32_t w, int32_t s, int32_t out_dtype, void* B);
+
+/* Preconditioner factor: Q = B B^T (eqn. pdprecond), Q = L L^T, and Linv = L^{-1}.
+ *   B    [device] m x w row-major, b_dtype IPM_F64 or IPM_F32
+ *   L    [device] m x m, or NULL; on return its lower triangle holds L (upper part unspecified)
+ *   Linv [device] m x m; on return the lower triangle holds L^{-1}, the upper part is zero
+ *   bad_pivot  [host] may be NULL; set to the first failing pivot index or -1.
+ * Errors: IPM_ERR_NOT_SPD if a pivot is not positive (B lacks full row rank). Synchronizes. */
+int ipm_precond_factor(ipm_ctx* ctx, int64_t m, int32_t w, int32_t b_dtype, const void* B,
+                       double* L, double* Linv, int64_t* bad_pivot);
+
+/* Preconditioned CG for A D^2 A^T dy = p with preconditioner Q = L L^T (Algorithm 1, step 3).
+ *   d2   [device] n doubles, the diagonal of D^2
+ *   Linv [device] m x m lower triangle of L^{-1} (as written by ipm_precond_factor)
+ *   p    [device] m doubles
+ *   dy   [device] m doubles; input: initial iterate if warm != 0 (kept only if its
+ *        preconditioned residual is below that of 0), output: the solution.
+ *   Stops when ||L^-1 (p - A D^2 A^T dy)|| <= tol_pcg * ||L^-1 p|| (eq. pdcond2), at maxit_pcg,
+ *   or when the residual stagnates (params stag_window / stag_ratio). Synchronizes. */
+int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* Linv,
+                  const double* p, double* dy, int32_t warm, const ipm_params* params,
+                  ipm_pcg_info* info);
+
+/* One iteration of Algorithm 3 (Section 5) from the state's point:
+ *   residuals r_p = A x - b, r_d = A^T y + s - c; stop test (relative gap, ||r_p||/(1+||b||),
+ *   ||r_d||/(1+||c||) all <= gap_tol -> IPM_CONVERGED, no step); W drawn for iteration k;
+ *   p = b - A (sigma mu / s + d^2 r_d); sketch, factor and CG as above; v of eq. compv with
+ *   (ADW)^+ = B^T Q^{-1} and the true residual A D^2 A^T dy - p; ds = -r_d - A^T dy;
+ *   dx = -x + sigma mu / s - d^2 ds - v / s; alpha_max = end of the segment inside N(gamma)
+ *   (x_i s_i >= (1-gamma) mu and ||r||/||r0|| <= mu/mu0 with r(alpha) = (1-alpha) r), times
+ *   theta if below 1; alpha = argmin of mu(alpha) on [0, alpha_max]; x, y, s updated in place
+ *   and k incremented only when the step succeeds. If CG fails (stagnation, maxit) or Q is not
+ *   SPD, W is redrawn up to max_redraws times with w doubled and s at least 2.
+ * Synchronizes. */
+int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* params,
+             ipm_step_info* info);
+
+/* ---- measurement ------------------------------------------------------------------------ */
+
+/* q = A diag(d2) A^T v in one pass over A (the CG matvec). v, q [device] m doubles;
+ * d2 [device] n doubles. */
+int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v,
+                      double* q);
+
+#define IPM_KERNEL_MATVEC  0   /* the CG matvec pass over A                               */
+#define IPM_KERNEL_SKETCH  1   /* the sketch pass over A                                  */
+#define IPM_KERNEL_GRAM    2   /* the Gram product B B^T                                  */
+#define IPM_KERNEL_COUNT   3
+
+/* Enable (1) or disable (0) per-kernel timing with HIP events recorded around every launch of
+ * the kernels above on the context's stream; enabling resets the totals. */
+int ipm_ctx_set_timing(ipm_ctx* ctx, int32_t on);
+/* Total milliseconds and number of launches of `kernel` since timing was enabled.
+ * Synchronizes. */
+int ipm_kernel_time(ipm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPMSK_H */

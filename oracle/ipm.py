@@ -336,6 +336,8 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
             return st, info
         dy = sla.cho_solve((L, True), p)
     else:
+        # Redraws: the accepted draw is the last one tried; a draw whose Q is not SPD is
+        # skipped unless it is the last allowed one (then the step fails).
         res = None
         for attempt in range(prm.max_redraws + 1):
             w, sk = sketch_size(prm.w, prm.s, attempt)
@@ -345,16 +347,16 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
             try:
                 L = sla.cholesky(Q, lower=True)
             except np.linalg.LinAlgError:
-                info.status = ERR_NOT_SPD
+                if attempt == prm.max_redraws:
+                    info.status = ERR_NOT_SPD
+                    info.extra.update(attempts=attempt + 1)
+                    return st, info
                 continue
             res = pcg(matvec, L, p, prm.tol_pcg, prm.maxit_pcg, dy0=dy0,
                       stag_window=prm.stag_window, stag_ratio=prm.stag_ratio)
-            info.status = OK
-            if res.status == OK:
+            if res.status in (OK, ERR_BREAKDOWN):
                 break
         info.extra.update(attempts=attempt + 1, w_used=w, s_used=sk)
-        if res is None:
-            return st, info
         info.pcg_iters, info.pcg_status, info.pcg_relres = res.iters, res.status, res.relres
         if res.status == ERR_BREAKDOWN:
             info.status = ERR_BREAKDOWN

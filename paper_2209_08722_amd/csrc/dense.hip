@@ -1,0 +1,229 @@
+// Dense FP64 linear algebra on the m x m preconditioner (m <= a few thousand):
+//   - the Gram product Q = B B^T of the sketch (eqn. pdprecond),
+//   - the Cholesky factor Q = L L^T (right-looking, 64-wide panels) and L^{-1},
+// all built from one MFMA GEMM kernel (v_mfma_f64_16x16x4f64) and a one-wave kernel that
+// factors and inverts a 64 x 64 diagonal block in LDS.
+#include <climits>
+
+#include "kernels.hpp"
+
+namespace ipmsk {
+
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 64;    // output tile edge
+constexpr int GK = 16;    // K step staged in LDS
+
+// C[M x N] = alpha * A[M x K] * op(B) (+ beta * C). A row-major (lda); op(B) = B^T with B stored
+// N x K (TRANS_B) or B stored K x N. 256 threads = 4 waves in a 2 x 2 grid of 32 x 32 sub-tiles,
+// each made of 2 x 2 MFMA 16 x 16 blocks.
+// MFMA f64 16x16x4 operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16]; element r
+// of lane l's 4-vector result is D[l/16 + 4*r][l%16] (checked on gfx950).
+template <bool TRANS_B, bool LOWER, typename TIN>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha, const TIN* A,
+                                              int64_t lda, const TIN* __restrict__ B, int64_t ldb, double beta,
+                                              double* C, int64_t ldc, int kchunk, int atomic) {
+    const int tm = blockIdx.y * GT, tn = blockIdx.x * GT;
+    if (LOWER && tn >= tm + GT) return;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    __shared__ double As[GT][GK + 1];
+    __shared__ double Bs[GT][GK + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = wid >> 1, wc = wid & 1;
+    d4_t acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid * 4 + q;
+            const int r = e >> 4, kk = e & 15;
+            const int gr = tm + r, gk = k0 + kk;
+            As[r][kk] = (gr < M && gk < kend) ? (double)A[(int64_t)gr * lda + gk] : 0.0;
+        }
+        if (TRANS_B) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = tid * 4 + q;
+                const int r = e >> 4, kk = e & 15;
+                const int gn = tn + r, gk = k0 + kk;
+                Bs[r][kk] = (gn < N && gk < kend) ? (double)B[(int64_t)gn * ldb + gk] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = tid * 4 + q;
+                const int kk = e >> 6, nn = e & 63;
+                const int gn = tn + nn, gk = k0 + kk;
+                Bs[nn][kk] = (gn < N && gk < kend) ? (double)B[(int64_t)gk * ldb + gn] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < GK / 4; ++ks) {
+            const int kq = ks * 4 + (lane >> 4);
+            const double a0 = As[wr * 32 + (lane & 15)][kq];
+            const double a1 = As[wr * 32 + 16 + (lane & 15)][kq];
+            const double b0 = Bs[wc * 32 + (lane & 15)][kq];
+            const double b1 = Bs[wc * 32 + 16 + (lane & 15)][kq];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = tm + wr * 32 + bi * 16 + (lane >> 4) + 4 * r;
+                const int col = tn + wc * 32 + bj * 16 + (lane & 15);
+                if (row < M && col < N) {
+                    const double v = alpha * acc[bi][bj][r];
+                    double* cp = C + (int64_t)row * ldc + col;
+                    if (atomic) unsafeAtomicAdd(cp, v);
+                    else *cp = (beta == 0.0) ? v : v + beta * (*cp);
+                }
+            }
+}
+
+// Factor the kb x kb diagonal block at (k0, k0) of the partially updated matrix in place
+// (lower triangle) and write its inverse into X's diagonal block (zero above the diagonal).
+// One wave; the block lives in LDS. A pivot that is not positive is recorded in *status
+// (smallest index wins) and replaced by 1 so the remaining work stays finite.
+__global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ Lw, int64_t ld, int k0, int kb,
+                                                   double* __restrict__ X, int64_t ldx, int* __restrict__ status) {
+    __shared__ double a[64][65];
+    __shared__ double xi[64][65];
+    const int t = threadIdx.x;
+    for (int i = 0; i < kb; ++i) a[i][t] = (t <= i) ? Lw[(int64_t)(k0 + i) * ld + k0 + t] : 0.0;
+    __syncthreads();
+    for (int c = 0; c < kb; ++c) {
+        double piv = a[c][c];
+        __syncthreads();
+        if (!(piv > 0.0)) {
+            if (t == 0) atomicMin(status, k0 + c);
+            piv = 1.0;
+        }
+        const double lcc = sqrt(piv);
+        if (t == c) a[c][c] = lcc;
+        if (t > c && t < kb) a[t][c] = a[t][c] / lcc;
+        __syncthreads();
+        if (t > c && t < kb) {
+            const double lic = a[t][c];
+            for (int j = c + 1; j <= t; ++j) a[t][j] -= lic * a[j][c];
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < kb; ++i)
+        if (t <= i) Lw[(int64_t)(k0 + i) * ld + k0 + t] = a[i][t];
+    if (t < kb) {
+        for (int i = 0; i < t; ++i) xi[i][t] = 0.0;
+        xi[t][t] = 1.0 / a[t][t];
+        for (int i = t + 1; i < kb; ++i) {
+            double s = 0.0;
+            for (int q = t; q < i; ++q) s += a[i][q] * xi[q][t];
+            xi[i][t] = -s / a[i][i];
+        }
+    }
+    __syncthreads();
+    for (int i = 0; i < kb; ++i)
+        if (t < kb) X[(int64_t)(k0 + i) * ldx + k0 + t] = xi[i][t];
+}
+
+__global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ X, double* __restrict__ XT, int m) {
+    __shared__ double tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int i = by + r, j = bx + tx;
+        tile[r][tx] = (i < m && j < m) ? X[(int64_t)i * m + j] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bx + r, j = by + tx;   // XT[i][j] = X[j][i]
+        if (i < m && j < m) XT[(int64_t)i * m + j] = tile[tx][r];
+    }
+}
+
+__global__ void k_fill(double* p, int64_t count, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_i32(int* p, int64_t count, int v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <bool TB, bool LO, typename TIN>
+hipError_t gemm_go(int M, int N, int K, double alpha, const TIN* A, int64_t lda, const TIN* B, int64_t ldb,
+                   double beta, double* C, int64_t ldc, int ksplit, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (ksplit < 1) ksplit = 1;
+    int kchunk = (K + ksplit - 1) / ksplit;
+    kchunk = ((kchunk + GK - 1) / GK) * GK;
+    if (kchunk < GK) kchunk = GK;
+    ksplit = K > 0 ? (K + kchunk - 1) / kchunk : 1;
+    const dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, ksplit);
+    hipLaunchKernelGGL((k_gemm<TB, LO, TIN>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                       kchunk, ksplit > 1 ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_dgemm(bool trans_b, bool lower_only, int M, int N, int K, double alpha, const double* A,
+                        int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int ksplit,
+                        hipStream_t st) {
+    if (trans_b) {
+        return lower_only ? gemm_go<true, true, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ksplit, st)
+                          : gemm_go<true, false, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ksplit, st);
+    }
+    return lower_only ? gemm_go<false, true, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ksplit, st)
+                      : gemm_go<false, false, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ksplit, st);
+}
+
+hipError_t launch_sgram_f32(int m, int w, const float* B, double* C, int ksplit, hipStream_t st) {
+    return gemm_go<true, true, float>(m, m, w, 1.0, B, w, B, w, 0.0, C, m, ksplit, st);
+}
+
+hipError_t launch_potrf_diag(double* Lw, int64_t ld, int k0, int kb, double* X, int64_t ldx, int* status,
+                             hipStream_t st) {
+    if (kb < 1 || kb > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, st, Lw, ld, k0, kb, X, ldx, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* X, double* XT, int m, hipStream_t st) {
+    const dim3 grid((m + 31) / 32, (m + 31) / 32);
+    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, X, XT, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+}  // namespace ipmsk

@@ -1,0 +1,709 @@
+// C ABI of the sketch-preconditioned IPM hot path: context, workspace and orchestration of the
+// HIP kernels. Declarations and the contract of every entry point are in include/ipmsk.h.
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ipmsk.h"
+#include "kernels.hpp"
+
+using namespace ipmsk;
+
+namespace {
+
+enum WsId {
+    W_PART = 0, W_COLPART, W_RED, W_D2, W_RD, W_DS, W_DX, W_RP, W_P, W_DY, W_RHAT, W_G1, W_G2, W_U, W_B,
+    W_L, W_X, W_XT, W_T, W_SCAL, W_PCG_VEC, W_PCG_RHO, W_PCG_CD, W_PCG_CI, W_STATUS, W_PART3, W_PARTMIN,
+    W_INFO, W_DQ, W_COUNT
+};
+
+struct TimedPair {
+    hipEvent_t a, b;
+    int tag;   // CG iteration index (or -1)
+};
+
+}  // namespace
+
+struct ipm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    std::string err;
+    void* ws[W_COUNT] = {};
+    size_t ws_bytes[W_COUNT] = {};
+    void* pinned = nullptr;   // host staging for scalar readbacks
+    bool timing = false;
+    std::vector<TimedPair> pending[IPM_KERNEL_COUNT];
+    double total_ms[IPM_KERNEL_COUNT] = {};
+    int64_t launches[IPM_KERNEL_COUNT] = {};
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+constexpr size_t kPinnedBytes = 4096;
+
+int fail(ipm_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(ctx, IPM_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define CHK(expr)                      \
+    do {                               \
+        int rc_ = (expr);              \
+        if (rc_ < 0) return rc_;       \
+    } while (0)
+
+int ensure(ipm_ctx* ctx, int id, size_t bytes, void** out) {
+    if (bytes == 0) bytes = 8;
+    if (ctx->ws_bytes[id] < bytes) {
+        if (ctx->ws[id]) {
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            HIPCHK(hipFree(ctx->ws[id]));
+            ctx->ws[id] = nullptr;
+            ctx->ws_bytes[id] = 0;
+        }
+        const size_t grow = bytes + bytes / 4;
+        void* p = nullptr;
+        if (hipMalloc(&p, grow) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, IPM_ERR_NOMEM, "workspace allocation of %zu bytes failed", grow);
+        }
+        ctx->ws[id] = p;
+        ctx->ws_bytes[id] = grow;
+    }
+    *out = ctx->ws[id];
+    return IPM_OK;
+}
+
+template <typename T>
+int ws(ipm_ctx* ctx, int id, size_t count, T** out) {
+    void* p = nullptr;
+    int rc = ensure(ctx, id, count * sizeof(T), &p);
+    *out = reinterpret_cast<T*>(p);
+    return rc;
+}
+
+hipEvent_t pool_event(ipm_ctx* ctx) {
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Begin/end a timed region around one launch of a measured kernel.
+struct Timer {
+    ipm_ctx* ctx;
+    int kernel;
+    int tag;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer(ipm_ctx* c, int k, int t = -1) : ctx(c), kernel(k), tag(t) {
+        if (ctx->timing) {
+            a = pool_event(ctx);
+            b = pool_event(ctx);
+            if (a) (void)hipEventRecord(a, ctx->stream);
+        }
+    }
+    void stop() {
+        if (ctx->timing && a && b) {
+            (void)hipEventRecord(b, ctx->stream);
+            ctx->pending[kernel].push_back(TimedPair{a, b, tag});
+            a = b = nullptr;
+        }
+    }
+};
+
+// Resolve pending timings; pairs tagged with a CG iteration >= keep_below are dropped (those
+// launches returned immediately because CG had already stopped).
+void resolve_timing(ipm_ctx* ctx, int kernel, int keep_below) {
+    for (auto& tp : ctx->pending[kernel]) {
+        if (tp.tag < 0 || tp.tag < keep_below) {
+            float ms = 0.f;
+            if (hipEventSynchronize(tp.b) == hipSuccess && hipEventElapsedTime(&ms, tp.a, tp.b) == hipSuccess) {
+                ctx->total_ms[kernel] += ms;
+                ctx->launches[kernel] += 1;
+            }
+        }
+        ctx->pool.push_back(tp.a);
+        ctx->pool.push_back(tp.b);
+    }
+    ctx->pending[kernel].clear();
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+int elem_size(int dtype) { return dtype == IPM_F64 ? 8 : (dtype == IPM_F32 ? 4 : (dtype == IPM_BF16 ? 2 : 0)); }
+
+int check_matrix(ipm_ctx* ctx, const ipm_matrix* A) {
+    if (!A) return fail(ctx, IPM_ERR_ARG, "A is null");
+    if (A->layout != IPM_DENSE_ROWMAJOR) return fail(ctx, IPM_ERR_ARG, "unsupported layout %d", A->layout);
+    const int es = elem_size(A->dtype);
+    if (!es) return fail(ctx, IPM_ERR_ARG, "unsupported dtype %d", A->dtype);
+    if (A->m < 1 || A->n < 1 || A->m > A->n) return fail(ctx, IPM_ERR_ARG, "need 1 <= m <= n (m=%lld n=%lld)",
+                                                          (long long)A->m, (long long)A->n);
+    if (A->m > 1 << 20) return fail(ctx, IPM_ERR_ARG, "m too large");
+    if (A->ld < A->n) return fail(ctx, IPM_ERR_ARG, "ld < n");
+    if (!A->val) return fail(ctx, IPM_ERR_ARG, "A->val is null");
+    if ((A->ld * es) % 16 != 0) return fail(ctx, IPM_ERR_ARG, "ld*elem_size must be a multiple of 16 bytes");
+    if (reinterpret_cast<uintptr_t>(A->val) % 16 != 0) return fail(ctx, IPM_ERR_ARG, "A->val must be 16-byte aligned");
+    return IPM_OK;
+}
+
+HashKeys make_keys(uint64_t seed, int64_t k, int w, int s) {
+    HashKeys hk{};
+    const uint64_t base = seed ^ mix64((uint64_t)k);
+    for (int r = 0; r < s; ++r) hk.key[r] = mix64(base + (uint64_t)(r + 1) * kPhi);
+    hk.s = s;
+    hk.blk = w / s;
+    hk.scale = 1.0 / std::sqrt((double)s);
+    return hk;
+}
+
+int do_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* dvals, int is_d2, const HashKeys& hk, int w,
+              int out_f64, void* B) {
+    const int m = (int)A->m;
+    const SketchPlan sp = sketch_plan(m, A->n, w, out_f64, ctx->num_cu);
+    if (sp.atomic) {
+        if (out_f64) {
+            HIPCHK(launch_fill(reinterpret_cast<double*>(B), (int64_t)m * w, 0.0, ctx->stream));
+        } else {
+            HIPCHK(hipMemsetAsync(B, 0, (size_t)m * w * sizeof(float), ctx->stream));
+        }
+    }
+    Timer t(ctx, IPM_KERNEL_SKETCH);
+    HIPCHK(launch_sketch(A->dtype, A->val, m, A->n, A->ld, dvals, is_d2, hk, w, out_f64, B, sp, ctx->stream));
+    t.stop();
+    return IPM_OK;
+}
+
+// Q = B B^T (lower), Q = L L^T in place in Lw, X = L^{-1}. Returns the first bad pivot or -1.
+int do_factor(ipm_ctx* ctx, int m, int w, int b_f64, const void* B, double* Lw, double* X, int64_t* bad) {
+    hipStream_t st = ctx->stream;
+    const int T = (m + 63) / 64;
+    const int tiles = T * (T + 1) / 2;
+    int ksplit = (2 * ctx->num_cu + tiles - 1) / tiles;
+    const int kmax = (w + 63) / 64;
+    if (ksplit > kmax) ksplit = kmax;
+    if (ksplit < 1) ksplit = 1;
+    if (ksplit > 1) HIPCHK(launch_fill(Lw, (int64_t)m * m, 0.0, st));
+    {
+        Timer t(ctx, IPM_KERNEL_GRAM);
+        if (b_f64)
+            HIPCHK(launch_dgemm(true, true, m, m, w, 1.0, reinterpret_cast<const double*>(B), w,
+                                reinterpret_cast<const double*>(B), w, 0.0, Lw, m, ksplit, st));
+        else
+            HIPCHK(launch_sgram_f32(m, w, reinterpret_cast<const float*>(B), Lw, ksplit, st));
+        t.stop();
+    }
+    int* status = nullptr;
+    CHK(ws(ctx, W_STATUS, 4, &status));
+    HIPCHK(launch_fill_i32(status, 1, INT_MAX, st));
+    HIPCHK(launch_fill(X, (int64_t)m * m, 0.0, st));
+    for (int k0 = 0; k0 < m; k0 += 64) {
+        const int kb = (m - k0) < 64 ? (m - k0) : 64;
+        HIPCHK(launch_potrf_diag(Lw, m, k0, kb, X, m, status, st));
+        const int rem = m - k0 - kb;
+        if (rem > 0) {
+            double* panel = Lw + (int64_t)(k0 + kb) * m + k0;
+            HIPCHK(launch_dgemm(true, false, rem, kb, kb, 1.0, panel, m, X + (int64_t)k0 * m + k0, m, 0.0, panel, m, 1,
+                                st));
+            HIPCHK(launch_dgemm(true, true, rem, rem, kb, -1.0, panel, m, panel, m, 1.0,
+                                Lw + (int64_t)(k0 + kb) * m + (k0 + kb), m, 1, st));
+        }
+    }
+    // X = L^{-1} by block rows: X[r, :r] = -X[r, r] * (L[r, :r] * X[:r, :r])
+    double* Tm = nullptr;
+    CHK(ws(ctx, W_T, (size_t)64 * m, &Tm));
+    for (int r0 = 64; r0 < m; r0 += 64) {
+        const int rb = (m - r0) < 64 ? (m - r0) : 64;
+        const int ntile = (r0 + 63) / 64;
+        int ks = ctx->num_cu / ntile;
+        if (ks > r0 / 64) ks = r0 / 64;
+        if (ks < 1) ks = 1;
+        if (ks > 1) HIPCHK(launch_fill(Tm, (int64_t)rb * m, 0.0, st));
+        HIPCHK(launch_dgemm(false, false, rb, r0, r0, 1.0, Lw + (int64_t)r0 * m, m, X, m, 0.0, Tm, m, ks, st));
+        HIPCHK(launch_dgemm(false, false, rb, r0, rb, -1.0, X + (int64_t)r0 * m + r0, m, Tm, m, 0.0,
+                            X + (int64_t)r0 * m, m, 1, st));
+    }
+    int* hs = reinterpret_cast<int*>(ctx->pinned);
+    HIPCHK(hipMemcpyAsync(hs, status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    resolve_timing(ctx, IPM_KERNEL_GRAM, INT_MAX);
+    *bad = (hs[0] == INT_MAX) ? -1 : hs[0];
+    return IPM_OK;
+}
+
+// One matvec pass over A: part <- partials of A diag(d2) A^T v.
+int matvec_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v, double* part,
+                const StripPlan& pl, const int* done, int tag) {
+    StripCall c{};
+    c.kind = STRIP_MATVEC;
+    c.dtype = A->dtype;
+    c.acc64 = 1;
+    c.A = A->val;
+    c.m = (int)A->m;
+    c.n = A->n;
+    c.ld = A->ld;
+    c.vec0 = v;
+    c.d2 = d2;
+    c.part = part;
+    c.done = done;
+    Timer t(ctx, IPM_KERNEL_MATVEC, tag);
+    HIPCHK(launch_strip(c, pl, ctx->stream));
+    t.stop();
+    return IPM_OK;
+}
+
+struct PcgOut {
+    int iters, status, warm_used;
+    double relres, rho_star;
+};
+
+// CG with preconditioner X^T X (X = L^{-1}); dy_out receives the solution.
+int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X, const double* p, double* dy_out,
+           int warm, const ipm_params* prm, PcgOut* out) {
+    hipStream_t st = ctx->stream;
+    const int m = (int)A->m;
+    double* XT = nullptr;
+    CHK(ws(ctx, W_XT, (size_t)m * m, &XT));
+    HIPCHK(launch_transpose(X, XT, m, st));
+    const StripPlan pl = strip_plan(A->dtype, m, A->n, ctx->num_cu, STRIP_MATVEC);
+    if (pl.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
+    double *part = nullptr, *vec = nullptr, *rho = nullptr, *cd = nullptr, *dq = nullptr, *info = nullptr;
+    int* ci = nullptr;
+    CHK(ws(ctx, W_PART, (size_t)pl.grid * m, &part));
+    CHK(ws(ctx, W_PCG_VEC, (size_t)8 * m, &vec));
+    const int gb = gemv_blocks(m);
+    CHK(ws(ctx, W_PCG_RHO, (size_t)2 * gb, &rho));
+    CHK(ws(ctx, W_PCG_CD, (size_t)PD_HIST + prm->maxit_pcg + 2, &cd));
+    CHK(ws(ctx, W_PCG_CI, PI_COUNT, &ci));
+    const int nred = reduce_rows_blocks(m);
+    CHK(ws(ctx, W_DQ, (size_t)nred, &dq));
+    CHK(ws(ctx, W_INFO, 8, &info));
+    PcgBufs b{};
+    b.m = m;
+    b.X = X;
+    b.XT = XT;
+    b.p = p;
+    b.dy[0] = vec;
+    b.dy[1] = vec + m;
+    b.r[0] = vec + 2 * m;
+    b.r[1] = vec + 3 * m;
+    b.dv = vec + 4 * m;
+    b.q = vec + 5 * m;
+    b.wv = vec + 6 * m;
+    b.wv2 = vec + 7 * m;
+    b.dq_part = dq;
+    b.n_dq = nred;
+    b.rho_part = rho;
+    b.n_rho = gb;
+    b.cd = cd;
+    b.ci = ci;
+    b.tol = prm->tol_pcg;
+    b.stag_ratio = prm->stag_ratio;
+    b.stag_window = prm->stag_window;
+    b.maxit = prm->maxit_pcg;
+    HIPCHK(launch_fill_i32(ci, PI_COUNT, 0, st));
+    if (warm) {
+        CHK(matvec_pass(ctx, A, d2, dy_out, part, pl, nullptr, -1));
+        HIPCHK(launch_reduce_rows(POST_PLAIN, part, pl.grid, m, 1, nullptr, nullptr, nullptr, b.q, nullptr, nullptr,
+                                  nullptr, st));
+    }
+    HIPCHK(launch_pcg_init1(b, warm, st));
+    HIPCHK(launch_pcg_init2(b, warm, dy_out, st));
+    int* hi = reinterpret_cast<int*>(ctx->pinned);
+    int j = 0;
+    int batch = 8;
+    const int* done = ci + PI_DONE;
+    for (;;) {
+        for (int t = 0; t < batch && j < prm->maxit_pcg; ++t, ++j) {
+            CHK(matvec_pass(ctx, A, d2, b.dv, part, pl, done, j));
+            HIPCHK(launch_reduce_rows(POST_MATVEC, part, pl.grid, m, 1, nullptr, nullptr, b.dv, b.q, nullptr, dq, done,
+                                      st));
+            HIPCHK(launch_pcg_gemv1(b, j, st));
+            HIPCHK(launch_pcg_gemv2(b, j, st));
+        }
+        HIPCHK(hipMemcpyAsync(hi, ci, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hi[PI_DONE] || j >= prm->maxit_pcg) break;
+        batch = 4;
+    }
+    HIPCHK(launch_pcg_finish(b, dy_out, info, st));
+    double* hd = reinterpret_cast<double*>(ctx->pinned);
+    HIPCHK(hipMemcpyAsync(hd, info, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    out->iters = (int)hd[0];
+    out->status = (int)hd[1];
+    out->warm_used = (int)hd[2];
+    out->relres = hd[3];
+    out->rho_star = hd[4];
+    resolve_timing(ctx, IPM_KERNEL_MATVEC, out->iters);
+    resolve_timing(ctx, IPM_KERNEL_SKETCH, INT_MAX);
+    return IPM_OK;
+}
+
+int check_params(ipm_ctx* ctx, const ipm_params* p, int64_t m) {
+    if (!p) return fail(ctx, IPM_ERR_ARG, "params is null");
+    if (!(p->sigma > 0 && p->sigma < 1)) return fail(ctx, IPM_ERR_ARG, "sigma must be in (0, 1)");
+    if (!(p->gamma > 0 && p->gamma < 1)) return fail(ctx, IPM_ERR_ARG, "gamma must be in (0, 1)");
+    if (!(p->theta > 0 && p->theta <= 1)) return fail(ctx, IPM_ERR_ARG, "theta must be in (0, 1]");
+    if (!(p->tol_pcg >= 0 && is_finite(p->tol_pcg))) return fail(ctx, IPM_ERR_ARG, "bad tol_pcg");
+    if (!(p->gap_tol >= 0 && is_finite(p->gap_tol))) return fail(ctx, IPM_ERR_ARG, "bad gap_tol");
+    if (!(p->stag_ratio > 0 && is_finite(p->stag_ratio))) return fail(ctx, IPM_ERR_ARG, "bad stag_ratio");
+    if (!(is_finite(p->min_step))) return fail(ctx, IPM_ERR_ARG, "bad min_step");
+    if (p->maxit_pcg < 1 || p->maxit_pcg > 100000) return fail(ctx, IPM_ERR_ARG, "maxit_pcg out of range");
+    if (p->stag_window < 1) return fail(ctx, IPM_ERR_ARG, "stag_window must be >= 1");
+    if (p->max_redraws < 0 || p->max_redraws > 6) return fail(ctx, IPM_ERR_ARG, "max_redraws out of range");
+    if (p->s < 1 || p->s > 8) return fail(ctx, IPM_ERR_ARG, "s must be in 1..8");
+    if (p->w < 1 || p->w % p->s != 0) return fail(ctx, IPM_ERR_ARG, "s must divide w");
+    if (p->w < m) return fail(ctx, IPM_ERR_ARG, "w (%d) must be >= m (%lld)", p->w, (long long)m);
+    return IPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ipm_params_default(ipm_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->sigma = 0.5;
+    p->gamma = 0.9;
+    p->theta = 0.9999;
+    p->tol_pcg = 1e-10;
+    p->gap_tol = 1e-8;
+    p->min_step = 1e-14;
+    p->stag_ratio = 0.99;
+    p->w = 0;
+    p->s = 2;
+    p->maxit_pcg = 500;
+    p->stag_window = 10;
+    p->max_redraws = 3;
+    p->vcorr = 1;
+    p->seed = 0;
+}
+
+int ipm_ctx_create(ipm_ctx** out, int device, void* hip_stream) {
+    if (!out) return IPM_ERR_ARG;
+    *out = nullptr;
+    ipm_ctx* ctx = new (std::nothrow) ipm_ctx();
+    if (!ctx) return IPM_ERR_NOMEM;
+    ctx->device = device;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return IPM_ERR_HIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->num_cu = prop.multiProcessorCount;
+    if (hipHostMalloc(&ctx->pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return IPM_ERR_HIP;
+    }
+    *out = ctx;
+    return IPM_OK;
+}
+
+void ipm_ctx_destroy(ipm_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int k = 0; k < IPM_KERNEL_COUNT; ++k) resolve_timing(ctx, k, INT_MAX);
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    for (int i = 0; i < W_COUNT; ++i)
+        if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+}
+
+int ipm_ctx_set_stream(ipm_ctx* ctx, void* hip_stream) {
+    if (!ctx) return IPM_ERR_ARG;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return IPM_OK;
+}
+
+const char* ipm_last_error(const ipm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int ipm_ctx_set_timing(ipm_ctx* ctx, int32_t on) {
+    if (!ctx) return IPM_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    for (int k = 0; k < IPM_KERNEL_COUNT; ++k) {
+        resolve_timing(ctx, k, INT_MAX);
+        ctx->total_ms[k] = 0.0;
+        ctx->launches[k] = 0;
+    }
+    ctx->timing = on != 0;
+    return IPM_OK;
+}
+
+int ipm_kernel_time(ipm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches) {
+    if (!ctx || kernel < 0 || kernel >= IPM_KERNEL_COUNT) return IPM_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "sync failed");
+    resolve_timing(ctx, kernel, INT_MAX);
+    if (total_ms) *total_ms = ctx->total_ms[kernel];
+    if (launches) *launches = ctx->launches[kernel];
+    return IPM_OK;
+}
+
+int ipm_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* d, uint64_t seed, int64_t k, int32_t w, int32_t s,
+               int32_t out_dtype, void* B) {
+    if (!ctx) return IPM_ERR_ARG;
+    CHK(check_matrix(ctx, A));
+    if (!d || !B) return fail(ctx, IPM_ERR_ARG, "null pointer");
+    if (s < 1 || s > 8 || w < 1 || w % s != 0) return fail(ctx, IPM_ERR_ARG, "need 1 <= s <= 8 and s | w");
+    if (out_dtype != IPM_F64 && out_dtype != IPM_F32) return fail(ctx, IPM_ERR_ARG, "B must be F64 or F32");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    const HashKeys hk = make_keys(seed, k, w, s);
+    CHK(do_sketch(ctx, A, d, 0, hk, w, out_dtype == IPM_F64, B));
+    return IPM_OK;
+}
+
+int ipm_precond_factor(ipm_ctx* ctx, int64_t m, int32_t w, int32_t b_dtype, const void* B, double* L, double* Linv,
+                       int64_t* bad_pivot) {
+    if (!ctx) return IPM_ERR_ARG;
+    if (bad_pivot) *bad_pivot = -1;
+    if (m < 1 || m > 65536 || w < 1 || !B || !Linv) return fail(ctx, IPM_ERR_ARG, "bad arguments");
+    if (b_dtype != IPM_F64 && b_dtype != IPM_F32) return fail(ctx, IPM_ERR_ARG, "B must be F64 or F32");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    double* Lw = L;
+    if (!Lw) CHK(ws(ctx, W_L, (size_t)m * m, &Lw));
+    int64_t bad = -1;
+    CHK(do_factor(ctx, (int)m, w, b_dtype == IPM_F64, B, Lw, Linv, &bad));
+    if (bad_pivot) *bad_pivot = bad;
+    if (bad >= 0) return fail(ctx, IPM_ERR_NOT_SPD, "Q is not positive definite (pivot %lld)", (long long)bad);
+    return IPM_OK;
+}
+
+int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* Linv, const double* p, double* dy,
+                  int32_t warm, const ipm_params* params, ipm_pcg_info* info) {
+    if (!ctx) return IPM_ERR_ARG;
+    CHK(check_matrix(ctx, A));
+    if (!d2 || !Linv || !p || !dy || !params) return fail(ctx, IPM_ERR_ARG, "null pointer");
+    if (params->maxit_pcg < 1 || params->stag_window < 1 || !(params->tol_pcg >= 0))
+        return fail(ctx, IPM_ERR_ARG, "bad CG parameters");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    PcgOut o{};
+    CHK(do_pcg(ctx, A, d2, Linv, p, dy, warm ? 1 : 0, params, &o));
+    if (info) {
+        info->iters = o.iters;
+        info->status = o.status;
+        info->warm_used = o.warm_used;
+        info->reserved = 0;
+        info->relres = o.relres;
+        info->rho_star = o.rho_star;
+    }
+    if (o.status == IPM_ERR_BREAKDOWN) return fail(ctx, IPM_ERR_BREAKDOWN, "CG breakdown (d^T M d <= 0)");
+    return o.status;
+}
+
+int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v, double* q) {
+    if (!ctx) return IPM_ERR_ARG;
+    CHK(check_matrix(ctx, A));
+    if (!d2 || !v || !q) return fail(ctx, IPM_ERR_ARG, "null pointer");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    const int m = (int)A->m;
+    const StripPlan pl = strip_plan(A->dtype, m, A->n, ctx->num_cu, STRIP_MATVEC);
+    if (pl.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
+    double* part = nullptr;
+    CHK(ws(ctx, W_PART, (size_t)pl.grid * m, &part));
+    CHK(matvec_pass(ctx, A, d2, v, part, pl, nullptr, -1));
+    HIPCHK(launch_reduce_rows(POST_PLAIN, part, pl.grid, m, 1, nullptr, nullptr, nullptr, q, nullptr, nullptr, nullptr,
+                              ctx->stream));
+    return IPM_OK;
+}
+
+int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* prm, ipm_step_info* info) {
+    if (!ctx) return IPM_ERR_ARG;
+    if (!prob || !state || !info) return fail(ctx, IPM_ERR_ARG, "null pointer");
+    std::memset(info, 0, sizeof(*info));
+    const ipm_matrix* A = &prob->A;
+    CHK(check_matrix(ctx, A));
+    CHK(check_params(ctx, prm, A->m));
+    if (!prob->b || !prob->c || !state->x || !state->y || !state->s) return fail(ctx, IPM_ERR_ARG, "null vector");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    hipStream_t st = ctx->stream;
+    const int m = (int)A->m;
+    const int64_t n = A->n;
+    const int Gn = pointwise_blocks(n);
+
+    double *d2, *rd, *ds, *dx, *rp, *p, *dyv, *rhat, *g1, *g2, *scal, *part3, *partmin, *colpart, *rp2part, *part;
+    CHK(ws(ctx, W_D2, n, &d2));
+    CHK(ws(ctx, W_RD, n, &rd));
+    CHK(ws(ctx, W_DS, n, &ds));
+    CHK(ws(ctx, W_DX, n, &dx));
+    CHK(ws(ctx, W_RP, m, &rp));
+    CHK(ws(ctx, W_P, m, &p));
+    CHK(ws(ctx, W_DY, m, &dyv));
+    CHK(ws(ctx, W_RHAT, m, &rhat));
+    CHK(ws(ctx, W_G1, m, &g1));
+    CHK(ws(ctx, W_G2, m, &g2));
+    CHK(ws(ctx, W_SCAL, SC_COUNT, &scal));
+    CHK(ws(ctx, W_PART3, (size_t)3 * Gn, &part3));
+    CHK(ws(ctx, W_PARTMIN, Gn, &partmin));
+    const StripPlan plr = strip_plan(IPM_F64 == A->dtype ? IPM_F64 : A->dtype, m, n, ctx->num_cu, STRIP_RESID);
+    if (plr.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
+    CHK(ws(ctx, W_COLPART, plr.grid, &colpart));
+    const int nred = reduce_rows_blocks(m);
+    CHK(ws(ctx, W_RED, nred, &rp2part));
+    CHK(ws(ctx, W_PART, (size_t)2 * plr.grid * m, &part));
+
+    // residuals, mu, p and the stop test at the current point (Algorithm 3, step 3)
+    HIPCHK(launch_stats(n, state->x, state->s, prob->c, d2, part3, st));
+    HIPCHK(launch_fin_stats(n, m, part3, Gn, prob->b, state->y, prm->sigma, scal, st));
+    {
+        StripCall c{};
+        c.kind = STRIP_RESID;
+        c.dtype = A->dtype;
+        c.acc64 = 1;
+        c.A = A->val;
+        c.m = m;
+        c.n = n;
+        c.ld = A->ld;
+        c.vec0 = state->y;
+        c.d2 = d2;
+        c.x = state->x;
+        c.s = state->s;
+        c.c = prob->c;
+        c.rd_out = rd;
+        c.scal = scal;
+        c.part = part;
+        c.colpart = colpart;
+        HIPCHK(launch_strip(c, plr, st));
+    }
+    HIPCHK(launch_reduce_rows(POST_RESID, part, plr.grid, m, 2, prob->b, nullptr, nullptr, rp, p, rp2part, nullptr, st));
+    const int set_ref = state->r0norm < 0.0 ? 1 : 0;
+    HIPCHK(launch_metrics(n, m, rp2part, nred, colpart, plr.grid, set_ref, state->mu0, state->r0norm, scal, st));
+    double* hs = reinterpret_cast<double*>(ctx->pinned);
+    HIPCHK(hipMemcpyAsync(hs, scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    info->k = state->k;
+    info->mu = hs[SC_MU];
+    info->gap = hs[SC_GAP];
+    info->relgap = hs[SC_RELGAP];
+    info->rp_rel = hs[SC_RPREL];
+    info->rd_rel = hs[SC_RDREL];
+    info->obj = hs[SC_OBJ];
+    if (set_ref) {
+        state->mu0 = hs[SC_MU0];
+        state->r0norm = hs[SC_R0NORM];
+    }
+    if (!is_finite(info->mu) || !is_finite(info->relgap)) return fail(ctx, IPM_ERR_ARG, "non-finite iterate or data");
+    const double worst = std::fmax(info->relgap, std::fmax(info->rp_rel, info->rd_rel));
+    if (worst <= prm->gap_tol) {
+        info->status = IPM_CONVERGED;
+        return IPM_CONVERGED;
+    }
+
+    // Algorithm 1 with redraws of W: sketch, factor, CG
+    const int wmax = prm->w << prm->max_redraws;
+    double *B = nullptr, *Lw = nullptr, *X = nullptr;
+    CHK(ws(ctx, W_B, (size_t)m * (size_t)wmax, &B));
+    CHK(ws(ctx, W_L, (size_t)m * m, &Lw));
+    CHK(ws(ctx, W_X, (size_t)m * m, &X));
+    HashKeys hk{};
+    int w_used = prm->w, s_used = prm->s;
+    PcgOut po{};
+    int attempts = 0;
+    for (int a = 0; a <= prm->max_redraws; ++a) {
+        attempts = a + 1;
+        w_used = prm->w << a;
+        s_used = a == 0 ? prm->s : (prm->s > 2 ? prm->s : 2);
+        const uint64_t seed_a = a == 0 ? prm->seed : prm->seed + (uint64_t)a * 0x632BE59BD9B4E019ull;
+        hk = make_keys(seed_a, state->k, w_used, s_used);
+        CHK(do_sketch(ctx, A, d2, 1, hk, w_used, 1, B));
+        int64_t bad = -1;
+        CHK(do_factor(ctx, m, w_used, 1, B, Lw, X, &bad));
+        if (bad >= 0) {
+            if (a == prm->max_redraws) {
+                info->attempts = attempts;
+                info->status = IPM_ERR_NOT_SPD;
+                return fail(ctx, IPM_ERR_NOT_SPD, "Q is not positive definite after %d draws", attempts);
+            }
+            continue;
+        }
+        CHK(do_pcg(ctx, A, d2, X, p, dyv, 0, prm, &po));
+        if (po.status == IPM_ERR_BREAKDOWN) {
+            info->status = IPM_ERR_BREAKDOWN;
+            return fail(ctx, IPM_ERR_BREAKDOWN, "CG breakdown");
+        }
+        if (po.status == IPM_OK) break;
+    }
+    info->attempts = attempts;
+    info->w_used = w_used;
+    info->s_used = s_used;
+    info->pcg_iters = po.iters;
+    info->pcg_status = po.status;
+    info->pcg_relres = po.relres;
+
+    // directions (eq. ipm_inf): ds, true residual, v, dx
+    {
+        const StripPlan pld = strip_plan(A->dtype, m, n, ctx->num_cu, STRIP_DIR);
+        StripCall c{};
+        c.kind = STRIP_DIR;
+        c.dtype = A->dtype;
+        c.acc64 = 1;
+        c.A = A->val;
+        c.m = m;
+        c.n = n;
+        c.ld = A->ld;
+        c.vec0 = dyv;
+        c.d2 = d2;
+        c.rd = rd;
+        c.ds_out = ds;
+        c.part = part;
+        HIPCHK(launch_strip(c, pld, st));
+        HIPCHK(launch_reduce_rows(POST_RHAT, part, pld.grid, m, 1, nullptr, p, nullptr, rhat, nullptr, nullptr, nullptr,
+                                  st));
+    }
+    double* u = nullptr;
+    CHK(ws(ctx, W_U, (size_t)wmax, &u));
+    if (prm->vcorr) {
+        double* XT = nullptr;
+        CHK(ws(ctx, W_XT, (size_t)m * m, &XT));   // written by do_pcg for this draw
+        HIPCHK(launch_trigemv(X, m, 1, rhat, g1, st));
+        HIPCHK(launch_trigemv(XT, m, 0, g1, g2, st));
+        HIPCHK(launch_btg(B, 1, m, w_used, g2, u, st));
+    }
+    HIPCHK(launch_dx(n, state->x, state->s, d2, ds, u, prm->vcorr, hk, scal, dx, part3, st));
+    HIPCHK(launch_fin_dx(part3, Gn, scal, st));
+    HIPCHK(launch_roots(n, state->x, state->s, dx, ds, prm->gamma, scal, partmin, st));
+    HIPCHK(launch_alpha(n, partmin, Gn, prm->gamma, prm->theta, prm->min_step, scal, st));
+    HIPCHK(launch_update(n, m, state->x, state->y, state->s, dx, dyv, ds, scal, st));
+    HIPCHK(hipMemcpyAsync(hs, scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    info->alpha_max = hs[SC_AMAX];
+    info->alpha = hs[SC_ABAR];
+    info->vnorm = std::sqrt(hs[SC_V2]);
+    if (hs[SC_STALL] != 0.0) {
+        info->status = IPM_ERR_STALL;
+        return fail(ctx, IPM_ERR_STALL, "step length %.3e below min_step", info->alpha);
+    }
+    state->k += 1;
+    info->status = po.status;
+    return po.status;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Launchers of the ipmsk device kernels (internal interface between the C ABI and the kernels).
+#pragma once
+
+#include "common.hpp"
+
+namespace ipmsk {
+
+// Slots of the per-step device scalar block (doubles).
+enum Scalar {
+    SC_XS = 0, SC_CTX, SC_C2, SC_MU, SC_SMU, SC_BTY, SC_B2, SC_RP2, SC_RD2,
+    SC_GAP, SC_RELGAP, SC_RPREL, SC_RDREL, SC_OBJ, SC_RNORM, SC_MU0, SC_R0NORM,
+    SC_A1, SC_A2, SC_V2, SC_AMAX, SC_ABAR, SC_STALL, SC_ROOT, SC_COUNT = 32
+};
+
+// Post-processing of the row reduction of strip-pass partials.
+enum RowPost { POST_PLAIN = 0, POST_MATVEC = 1, POST_RESID = 2, POST_RHAT = 3 };
+
+// Kinds of single-pass strip kernels over row-major A.
+enum StripKind { STRIP_MATVEC = 0, STRIP_RESID = 1, STRIP_DIR = 2 };
+
+struct StripPlan {
+    int nt;        // threads per block (256 or 1024)
+    int rpt;       // rows per thread (template instance)
+    int grid;      // blocks (persistent)
+    int nstrips;   // column strips of width sw
+    int sw;        // strip width in columns
+    size_t lds;    // dynamic LDS bytes
+};
+
+// Arguments of every strip pass. Unused pointers may be null.
+struct StripCall {
+    int kind;
+    int dtype;               // IPM_F64 / IPM_F32 / IPM_BF16
+    int acc64;               // 1: FP64 accumulation, 0: FP32 (mixed-precision matvec)
+    const void* A;
+    int m;
+    int64_t n, ld;
+    const double* vec0;      // m-vector dotted with every column
+    const double* d2;        // n: diagonal of D^2
+    const double* x;         // n (resid)
+    const double* s;         // n (resid)
+    const double* c;         // n (resid)
+    const double* rd;        // n (dir: input r_d)
+    double* rd_out;          // n (resid: output r_d)
+    double* ds_out;          // n (dir: output ds)
+    const double* scal;      // device scalar block (resid reads SC_SMU)
+    double* part;            // [nacc][grid][m] partial row sums
+    double* colpart;         // [grid] partial per-column reductions (resid: sum r_d^2)
+    const int* done;         // early-exit flag (may be null)
+};
+
+StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind);
+hipError_t launch_strip(const StripCall& c, const StripPlan& p, hipStream_t st);
+
+// Row reduction of partials: out0/out1 as described by RowPost; blockpart gets per-block sums
+// (matvec: d^T q with d = dvec; resid: ||r_p||^2). Returns the number of blocks used.
+int reduce_rows_blocks(int m);
+hipError_t launch_reduce_rows(int post, const double* part, int G, int m, int nacc,
+                              const double* b, const double* pvec, const double* dvec,
+                              double* out0, double* out1, double* blockpart, const int* done,
+                              hipStream_t st);
+
+// ---- sketch and perturbation -----------------------------------------------------------------
+struct SketchPlan { int rows_per_block; int chunks; int64_t cols_per_chunk; size_t lds; bool atomic; bool global_only; };
+SketchPlan sketch_plan(int m, int64_t n, int w, int out_f64, int num_cu);
+hipError_t launch_sketch(int dtype, const void* A, int m, int64_t n, int64_t ld, const double* dvals,
+                         int dvals_are_d2, const HashKeys& hk, int w, int out_f64, void* B,
+                         const SketchPlan& sp, hipStream_t st);
+// u = B^T g (B m x w, FP64 or FP32); u is overwritten.
+hipError_t launch_btg(const void* B, int b_f64, int m, int w, const double* g, double* u, hipStream_t st);
+// dx and the sums a1 = x^T ds + s^T dx, a2 = dx^T ds, ||v||^2 as per-block partials [grid][3].
+int pointwise_blocks(int64_t n);
+hipError_t launch_dx(int64_t n, const double* x, const double* s, const double* d2, const double* ds,
+                     const double* u, int vcorr, const HashKeys& hk, const double* scal, double* dx,
+                     double* part3, hipStream_t st);
+
+// ---- dense FP64 linear algebra ----------------------------------------------------------------
+// C = alpha * A * op(B) + beta * C, row-major; op(B) = B^T (B stored N x K) if trans_b.
+// lower_only skips tiles strictly above the diagonal. ksplit > 1 accumulates atomically (C must
+// hold beta*C already; beta is ignored).
+hipError_t launch_dgemm(bool trans_b, bool lower_only, int M, int N, int K, double alpha,
+                        const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                        double* C, int64_t ldc, int ksplit, hipStream_t st);
+hipError_t launch_sgram_f32(int m, int w, const float* B, double* C, int ksplit, hipStream_t st);
+hipError_t launch_potrf_diag(double* Lw, int64_t ld, int k0, int kb, double* X, int64_t ldx, int* status,
+                             hipStream_t st);
+hipError_t launch_transpose(const double* X, double* XT, int m, hipStream_t st);
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st);
+
+// ---- PCG -----------------------------------------------------------------------------------------
+enum PcgInt { PI_DONE = 0, PI_STATUS, PI_ITERS, PI_WARM, PI_COUNT = 8 };
+enum PcgDbl { PD_RHO0 = 0, PD_RHO1, PD_RHOSTAR, PD_HIST = 8 };
+
+struct PcgBufs {
+    int m;
+    const double* X;      // L^{-1}, lower, ld m
+    const double* XT;     // (L^{-1})^T, upper, ld m
+    const double* p;
+    double* dy[2];
+    double* r[2];
+    double* dv;           // search direction
+    double* q;            // A D^2 A^T dv
+    double* wv;           // L^{-1} r
+    double* wv2;          // second right-hand side (warm start)
+    const double* dq_part;
+    int n_dq;
+    double* rho_part;
+    int n_rho;
+    double* cd;           // PcgDbl block (hist at PD_HIST)
+    int* ci;              // PcgInt block
+    double tol;
+    double stag_ratio;
+    int stag_window;
+    int maxit;
+};
+int gemv_blocks(int m);
+hipError_t launch_pcg_init1(const PcgBufs& b, int warm, hipStream_t st);
+hipError_t launch_pcg_init2(const PcgBufs& b, int warm, const double* dy_in, hipStream_t st);
+hipError_t launch_pcg_gemv1(const PcgBufs& b, int j, hipStream_t st);
+hipError_t launch_pcg_gemv2(const PcgBufs& b, int j, hipStream_t st);
+hipError_t launch_pcg_finish(const PcgBufs& b, double* dy_out, double* info_out, hipStream_t st);
+// y = L^{-1} x (lower) or (L^{-1})^T x (upper, given XT) - plain triangular GEMV.
+hipError_t launch_trigemv(const double* M, int m, int lower, const double* xin, double* yout, hipStream_t st);
+
+// ---- IPM step pointwise kernels -------------------------------------------------------------
+hipError_t launch_stats(int64_t n, const double* x, const double* s, const double* c, double* d2,
+                        double* part3, hipStream_t st);
+hipError_t launch_fin_stats(int64_t n, int m, const double* part3, int G, const double* b, const double* y,
+                            double sigma, double* scal, hipStream_t st);
+hipError_t launch_metrics(int64_t n, int m, const double* rp2part, int Grp, const double* rd2part, int Grd,
+                          int set_ref, double mu0_in, double r0_in, double* scal, hipStream_t st);
+hipError_t launch_fin_dx(const double* part3, int G, double* scal, hipStream_t st);
+hipError_t launch_roots(int64_t n, const double* x, const double* s, const double* dx, const double* ds,
+                        double gamma, const double* scal, double* partmin, hipStream_t st);
+hipError_t launch_alpha(int64_t n, const double* partmin, int G, double gamma, double theta,
+                        double min_step, double* scal, hipStream_t st);
+hipError_t launch_update(int64_t n, int m, double* x, double* y, double* s, const double* dx,
+                         const double* dy, const double* ds, const double* scal, hipStream_t st);
+
+}  // namespace ipmsk

@@ -1,0 +1,232 @@
+// Preconditioned CG for A D^2 A^T dy = p with preconditioner Q = L L^T (Algorithm 1, step 3;
+// CG on the system of eq. precond_alt written in its preconditioned form, eq. precond).
+//
+// The preconditioner is applied as two triangular GEMVs with X = L^{-1} and X^T, computed once
+// per IPM iteration: z = X^T (X r). The paper's residual norm ||Q^{-1/2} r|| equals ||X r||,
+// which is the CG scalar rho = r^T z.
+//
+// All CG scalars live on the device. One iteration is four launches:
+//   matvec pass (strip kernel) -> row reduction (q = A D^2 A^T d and partial d^T q)
+//   -> gemv1: alpha, dy += alpha d, r -= alpha q, w = X r, partial ||w||^2
+//   -> gemv2: rho', beta, d = X^T w + beta d, stop tests.
+// A device flag ends the iteration; kernels of later, already queued iterations return at once,
+// so the host queues iterations in batches and reads the flag once per batch. dy and r are
+// double-buffered by iteration parity because block 0 writes the new values while other blocks
+// still read the old ones.
+#include "kernels.hpp"
+
+namespace ipmsk {
+
+namespace {
+
+constexpr int GNT = 256;       // threads per GEMV block
+constexpr int GNW = GNT / 64;  // rows in flight per block (one wave per row)
+
+__device__ __forceinline__ double row_dot_lower(const double* __restrict__ M, int m, int row, const double* xs,
+                                                int lane) {
+    const double* mr = M + (int64_t)row * m;
+    double acc = 0.0;
+    for (int l = lane; l <= row; l += 64) acc += mr[l] * xs[l];
+    return wave_sum(acc);
+}
+
+__device__ __forceinline__ double row_dot_upper(const double* __restrict__ M, int m, int row, const double* xs,
+                                                int lane) {
+    const double* mr = M + (int64_t)row * m;
+    double acc = 0.0;
+    for (int l = row + lane; l < m; l += 64) acc += mr[l] * xs[l];
+    return wave_sum(acc);
+}
+
+__global__ __launch_bounds__(GNT) void k_pcg_init1(PcgBufs b, int warm) {
+    extern __shared__ double xs[];   // [2][m]
+    __shared__ double sh[GNW];
+    const int m = b.m, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int l = tid; l < m; l += GNT) {
+        xs[l] = b.p[l];
+        if (warm) xs[m + l] = b.p[l] - b.q[l];
+    }
+    __syncthreads();
+    double s1 = 0.0, s2 = 0.0;
+    for (int row = blockIdx.x * GNW + wid; row < m; row += gridDim.x * GNW) {
+        const double w1 = row_dot_lower(b.X, m, row, xs, lane);
+        if (lane == 0) { b.wv[row] = w1; s1 += w1 * w1; }
+        if (warm) {
+            const double w2 = row_dot_lower(b.X, m, row, xs + m, lane);
+            if (lane == 0) { b.wv2[row] = w2; s2 += w2 * w2; }
+        }
+    }
+    const double t1 = block_sum(s1, sh);
+    const double t2 = block_sum(s2, sh);
+    if (tid == 0) { b.rho_part[2 * blockIdx.x] = t1; b.rho_part[2 * blockIdx.x + 1] = t2; }
+}
+
+__global__ __launch_bounds__(GNT) void k_pcg_init2(PcgBufs b, int warm, const double* __restrict__ dy_in) {
+    extern __shared__ double xs[];   // [m]
+    __shared__ double sh[GNW];
+    const int m = b.m, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const double rs = sum_partials(b.rho_part, b.n_rho, 2, sh);
+    const double rr = warm ? sum_partials(b.rho_part + 1, b.n_rho, 2, sh) : 0.0;
+    const bool use_warm = warm && (rr < rs);
+    const double rho0 = use_warm ? rr : rs;
+    for (int l = tid; l < m; l += GNT) {
+        xs[l] = use_warm ? b.wv2[l] : b.wv[l];
+        if (blockIdx.x == 0) {
+            b.r[0][l] = use_warm ? b.p[l] - b.q[l] : b.p[l];
+            b.dy[0][l] = use_warm ? dy_in[l] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int row = blockIdx.x * GNW + wid; row < m; row += gridDim.x * GNW) {
+        const double z = row_dot_upper(b.XT, m, row, xs, lane);
+        if (lane == 0) b.dv[row] = z;
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        b.cd[PD_RHO0] = rho0;
+        b.cd[PD_RHOSTAR] = rs;
+        b.cd[PD_HIST] = sqrt(rho0);
+        b.ci[PI_WARM] = use_warm ? 1 : 0;
+        b.ci[PI_ITERS] = 0;
+        b.ci[PI_STATUS] = 0;
+        b.ci[PI_DONE] = (sqrt(rho0) <= b.tol * sqrt(rs)) ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(GNT) void k_pcg_gemv1(PcgBufs b, int j) {
+    if (b.ci[PI_DONE]) return;
+    extern __shared__ double xs[];   // [m]
+    __shared__ double sh[GNW];
+    const int m = b.m, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int par = j & 1;
+    const double dq = sum_partials(b.dq_part, b.n_dq, 1, sh);
+    if (!(dq > 0.0)) {
+        if (blockIdx.x == 0 && tid == 0) {
+            b.ci[PI_STATUS] = -4;   // IPM_ERR_BREAKDOWN
+            b.ci[PI_ITERS] = j;
+            b.ci[PI_DONE] = 1;
+        }
+        return;
+    }
+    const double alpha = b.cd[PD_RHO0 + par] / dq;
+    const double* __restrict__ rin = b.r[par];
+    for (int l = tid; l < m; l += GNT) {
+        const double rn = rin[l] - alpha * b.q[l];
+        xs[l] = rn;
+        if (blockIdx.x == 0) {
+            b.r[par ^ 1][l] = rn;
+            b.dy[par ^ 1][l] = b.dy[par][l] + alpha * b.dv[l];
+        }
+    }
+    __syncthreads();
+    double s = 0.0;
+    for (int row = blockIdx.x * GNW + wid; row < m; row += gridDim.x * GNW) {
+        const double w = row_dot_lower(b.X, m, row, xs, lane);
+        if (lane == 0) { b.wv[row] = w; s += w * w; }
+    }
+    const double t = block_sum(s, sh);
+    if (tid == 0) b.rho_part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(GNT) void k_pcg_gemv2(PcgBufs b, int j) {
+    if (b.ci[PI_DONE]) return;
+    extern __shared__ double xs[];   // [m]
+    __shared__ double sh[GNW];
+    const int m = b.m, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int par = j & 1;
+    const double rho_new = sum_partials(b.rho_part, b.n_rho, 1, sh);
+    const double beta = rho_new / b.cd[PD_RHO0 + par];
+    for (int l = tid; l < m; l += GNT) xs[l] = b.wv[l];
+    __syncthreads();
+    for (int row = blockIdx.x * GNW + wid; row < m; row += gridDim.x * GNW) {
+        const double z = row_dot_upper(b.XT, m, row, xs, lane);
+        if (lane == 0) b.dv[row] = z + beta * b.dv[row];
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        const double res = sqrt(rho_new);
+        double* hist = b.cd + PD_HIST;
+        hist[j + 1] = res;
+        b.cd[PD_RHO0 + (par ^ 1)] = rho_new;
+        const int it = j + 1;
+        int stop = 0, status = 0;
+        if (res <= b.tol * sqrt(b.cd[PD_RHOSTAR])) {
+            stop = 1;
+        } else if (it >= b.stag_window && res > b.stag_ratio * hist[it - b.stag_window]) {
+            stop = 1; status = 3;   // IPM_PCG_STAGNATED
+        } else if (it >= b.maxit) {
+            stop = 1; status = 2;   // IPM_PCG_MAXIT
+        }
+        if (stop) {
+            b.ci[PI_STATUS] = status;
+            b.ci[PI_ITERS] = it;
+            b.ci[PI_DONE] = 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(GNT) void k_pcg_finish(PcgBufs b, double* __restrict__ dy_out,
+                                                    double* __restrict__ info) {
+    const int it = b.ci[PI_ITERS];
+    const double* src = b.dy[it & 1];
+    for (int l = blockIdx.x * GNT + threadIdx.x; l < b.m; l += gridDim.x * GNT) dy_out[l] = src[l];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double rs = b.cd[PD_RHOSTAR];
+        info[0] = (double)it;
+        info[1] = (double)b.ci[PI_STATUS];
+        info[2] = (double)b.ci[PI_WARM];
+        info[3] = rs > 0.0 ? b.cd[PD_HIST + it] / sqrt(rs) : 0.0;
+        info[4] = rs;
+    }
+}
+
+__global__ __launch_bounds__(GNT) void k_trigemv(const double* __restrict__ M, int m, int lower,
+                                                 const double* __restrict__ xin, double* __restrict__ yout) {
+    extern __shared__ double xs[];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int l = tid; l < m; l += GNT) xs[l] = xin[l];
+    __syncthreads();
+    for (int row = blockIdx.x * GNW + wid; row < m; row += gridDim.x * GNW) {
+        const double v = lower ? row_dot_lower(M, m, row, xs, lane) : row_dot_upper(M, m, row, xs, lane);
+        if (lane == 0) yout[row] = v;
+    }
+}
+
+}  // namespace
+
+int gemv_blocks(int m) {
+    int g = (m + GNW - 1) / GNW;
+    return g > 1024 ? 1024 : g;
+}
+
+hipError_t launch_pcg_init1(const PcgBufs& b, int warm, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_init1, dim3(gemv_blocks(b.m)), dim3(GNT), sizeof(double) * 2 * b.m, st, b, warm);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_init2(const PcgBufs& b, int warm, const double* dy_in, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_init2, dim3(gemv_blocks(b.m)), dim3(GNT), sizeof(double) * b.m, st, b, warm, dy_in);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_gemv1(const PcgBufs& b, int j, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_gemv1, dim3(gemv_blocks(b.m)), dim3(GNT), sizeof(double) * b.m, st, b, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_gemv2(const PcgBufs& b, int j, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_gemv2, dim3(gemv_blocks(b.m)), dim3(GNT), sizeof(double) * b.m, st, b, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_finish(const PcgBufs& b, double* dy_out, double* info_out, hipStream_t st) {
+    int g = (b.m + GNT - 1) / GNT;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_pcg_finish, dim3(g), dim3(GNT), 0, st, b, dy_out, info_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_trigemv(const double* M, int m, int lower, const double* xin, double* yout, hipStream_t st) {
+    hipLaunchKernelGGL(k_trigemv, dim3(gemv_blocks(m)), dim3(GNT), sizeof(double) * m, st, M, m, lower, xin, yout);
+    return hipGetLastError();
+}
+
+}  // namespace ipmsk

@@ -1,0 +1,251 @@
+// The sparse-embedding sketch B = A D W (Algorithm 1, step 1; W from Section 2) and the
+// perturbation v = (XS)^{1/2} W (ADW)^+ r of eq. compv (Section 4), which reuses the same W.
+//
+// Sketch: a block owns R rows of A and a range of columns. Its threads stream along the rows
+// (consecutive threads read consecutive columns, so every load is coalesced), hash each column
+// once into its s buckets and signs, and scatter-add sign * d_j * A[i][j] / sqrt(s) into an
+// LDS-resident R x w bucket array with LDS atomics. When one block covers all columns of its
+// rows the bucket array is stored to B; otherwise blocks add their arrays into B with global
+// atomics. W is never stored: the hash is recomputed wherever W is applied.
+#include "kernels.hpp"
+
+namespace ipmsk {
+
+namespace {
+
+constexpr int SNT = 256;
+constexpr int SUNROLL = 4;    // columns per thread per pass (independent loads in flight)
+
+template <typename T, typename BT, int R>
+__global__ __launch_bounds__(SNT) void k_sketch_lds(const T* __restrict__ A, int m, int64_t n, int64_t ld,
+                                                    const double* __restrict__ dv, int d_is_d2, HashKeys hk, int w,
+                                                    int64_t cpc, BT* __restrict__ B, int atomic) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    BT* bk = reinterpret_cast<BT*>(smem_raw);   // [R][w]
+    const int tid = threadIdx.x;
+    const int row0 = blockIdx.x * R;
+    const int64_t jb = (int64_t)blockIdx.y * cpc;
+    const int64_t je = (jb + cpc < n) ? jb + cpc : n;
+    for (int i = tid; i < R * w; i += SNT) bk[i] = (BT)0;
+    __syncthreads();
+    const int s = hk.s;
+    for (int64_t jj = jb + tid; jj < je; jj += (int64_t)SNT * SUNROLL) {
+        BT av[SUNROLL][R];
+        double dj[SUNROLL];
+#pragma unroll
+        for (int u = 0; u < SUNROLL; ++u) {
+            const int64_t j = jj + (int64_t)u * SNT;
+            const bool ok = j < je;
+            double dd = ok ? dv[ok ? j : 0] : 0.0;
+            dj[u] = d_is_d2 ? sqrt(dd) : dd;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int i = row0 + rr;
+                av[u][rr] = (ok && i < m) ? (BT)Elem<T>::load1(A + (int64_t)i * ld + j) : (BT)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SUNROLL; ++u) {
+            const int64_t j = jj + (int64_t)u * SNT;
+            if (j >= je) continue;
+            for (int r = 0; r < s; ++r) {
+                int bucket;
+                double sign;
+                w_entry(hk, r, (uint64_t)j, bucket, sign);
+                const BT coef = (BT)(sign * dj[u] * hk.scale);
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) atomicAdd(&bk[rr * w + bucket], coef * av[u][rr]);
+            }
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < R * w; idx += SNT) {
+        const int rr = idx / w, bcol = idx - rr * w;
+        const int i = row0 + rr;
+        if (i < m) {
+            BT* dst = B + (int64_t)i * w + bcol;
+            if (atomic) unsafeAtomicAdd(dst, bk[idx]);
+            else *dst = bk[idx];
+        }
+    }
+}
+
+// Fallback when one row of buckets does not fit in LDS: scatter straight into B with global
+// atomics (B zeroed first).
+template <typename T, typename BT>
+__global__ __launch_bounds__(SNT) void k_sketch_global(const T* __restrict__ A, int m, int64_t n, int64_t ld,
+                                                       const double* __restrict__ dv, int d_is_d2, HashKeys hk,
+                                                       int w, BT* __restrict__ B) {
+    const int i = blockIdx.y;
+    for (int64_t j = (int64_t)blockIdx.x * SNT + threadIdx.x; j < n; j += (int64_t)gridDim.x * SNT) {
+        const double dd = dv[j];
+        const double djv = d_is_d2 ? sqrt(dd) : dd;
+        const double a = (double)Elem<T>::load1(A + (int64_t)i * ld + j);
+        for (int r = 0; r < hk.s; ++r) {
+            int bucket;
+            double sign;
+            w_entry(hk, r, (uint64_t)j, bucket, sign);
+            unsafeAtomicAdd(&B[(int64_t)i * w + bucket], (BT)(sign * djv * hk.scale * a));
+        }
+    }
+}
+
+template <typename T, typename BT, int R>
+void sketch_go(const T* A, int m, int64_t n, int64_t ld, const double* dv, int d2, const HashKeys& hk, int w,
+               BT* B, const SketchPlan& sp, hipStream_t st) {
+    const dim3 grid((m + R - 1) / R, sp.chunks);
+    hipLaunchKernelGGL((k_sketch_lds<T, BT, R>), grid, dim3(SNT), sp.lds, st, A, m, n, ld, dv, d2, hk, w,
+                       sp.cols_per_chunk, B, sp.atomic ? 1 : 0);
+}
+
+template <typename T, typename BT>
+hipError_t sketch_type(const void* Av, int m, int64_t n, int64_t ld, const double* dv, int d2, const HashKeys& hk,
+                       int w, void* Bv, const SketchPlan& sp, hipStream_t st) {
+    const T* A = reinterpret_cast<const T*>(Av);
+    BT* B = reinterpret_cast<BT*>(Bv);
+    if (sp.global_only) {
+        int gx = (int)((n + SNT - 1) / SNT);
+        if (gx > 64) gx = 64;
+        hipLaunchKernelGGL((k_sketch_global<T, BT>), dim3(gx, m), dim3(SNT), 0, st, A, m, n, ld, dv, d2, hk, w, B);
+        return hipGetLastError();
+    }
+    switch (sp.rows_per_block) {
+        case 1: sketch_go<T, BT, 1>(A, m, n, ld, dv, d2, hk, w, B, sp, st); break;
+        case 2: sketch_go<T, BT, 2>(A, m, n, ld, dv, d2, hk, w, B, sp, st); break;
+        case 4: sketch_go<T, BT, 4>(A, m, n, ld, dv, d2, hk, w, B, sp, st); break;
+        case 8: sketch_go<T, BT, 8>(A, m, n, ld, dv, d2, hk, w, B, sp, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// u = B^T g: thread per bucket column, block rows chunked; partial sums added atomically.
+template <typename BT>
+__global__ __launch_bounds__(256) void k_btg(const BT* __restrict__ B, int m, int w, int rows_per_chunk,
+                                             const double* __restrict__ g, double* __restrict__ u) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int i0 = blockIdx.y * rows_per_chunk;
+    const int i1 = min(m, i0 + rows_per_chunk);
+    if (b >= w) return;
+    double acc = 0.0;
+    for (int i = i0; i < i1; ++i) acc += (double)B[(int64_t)i * w + b] * g[i];
+    unsafeAtomicAdd(&u[b], acc);
+}
+
+// dx_j = -x_j + sigma mu / s_j - d2_j ds_j - v_j / s_j with
+// v_j = sqrt(x_j s_j) * sum_r sign_r(j) u[bucket_r(j)] / sqrt(s)   (eq. compv; eq. delxhat_i)
+// plus per-block sums of x ds + s dx, dx ds and v^2.
+__global__ __launch_bounds__(256) void k_dx(int64_t n, const double* __restrict__ x, const double* __restrict__ s,
+                                            const double* __restrict__ d2, const double* __restrict__ ds,
+                                            const double* __restrict__ u, int vcorr, HashKeys hk,
+                                            const double* __restrict__ scal, double* __restrict__ dx,
+                                            double* __restrict__ part3) {
+    __shared__ double sh[4];
+    const double smu = scal[SC_SMU];
+    double a1 = 0.0, a2 = 0.0, v2 = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+        const double xj = x[j], sj = s[j], dsj = ds[j];
+        double v = 0.0;
+        if (vcorr) {
+            double acc = 0.0;
+            for (int r = 0; r < hk.s; ++r) {
+                int bucket;
+                double sign;
+                w_entry(hk, r, (uint64_t)j, bucket, sign);
+                acc += sign * u[bucket];
+            }
+            v = sqrt(xj * sj) * acc * hk.scale;
+        }
+        const double dxj = -xj + smu / sj - d2[j] * dsj - v / sj;
+        dx[j] = dxj;
+        a1 += xj * dsj + sj * dxj;
+        a2 += dxj * dsj;
+        v2 += v * v;
+    }
+    const double t1 = block_sum(a1, sh);
+    const double t2 = block_sum(a2, sh);
+    const double t3 = block_sum(v2, sh);
+    if (threadIdx.x == 0) {
+        part3[3 * blockIdx.x] = t1;
+        part3[3 * blockIdx.x + 1] = t2;
+        part3[3 * blockIdx.x + 2] = t3;
+    }
+}
+
+}  // namespace
+
+SketchPlan sketch_plan(int m, int64_t n, int w, int out_f64, int num_cu) {
+    SketchPlan sp{};
+    const size_t esz = out_f64 ? 8 : 4;
+    const size_t budget_small = 64 * 1024, budget_max = 160 * 1024;
+    int R = 0;
+    for (int r : {8, 4, 2, 1})
+        if ((size_t)r * w * esz <= budget_small && r <= m) { R = r; break; }
+    if (R == 0 && (size_t)w * esz <= budget_max) R = 1;
+    if (R == 0) { sp.global_only = true; sp.atomic = true; sp.chunks = 1; sp.cols_per_chunk = n; return sp; }
+    sp.rows_per_block = R;
+    const int row_blocks = (m + R - 1) / R;
+    const int target = 2 * num_cu;
+    int chunks = (target + row_blocks - 1) / row_blocks;
+    const int64_t max_chunks = (n + 4095) / 4096;   // keep at least 4096 columns per block
+    if (chunks > max_chunks) chunks = (int)max_chunks;
+    if (chunks < 1) chunks = 1;
+    sp.chunks = chunks;
+    sp.cols_per_chunk = (n + chunks - 1) / chunks;
+    sp.atomic = chunks > 1;
+    sp.lds = (size_t)R * w * esz;
+    return sp;
+}
+
+hipError_t launch_sketch(int dtype, const void* A, int m, int64_t n, int64_t ld, const double* dvals,
+                         int dvals_are_d2, const HashKeys& hk, int w, int out_f64, void* B, const SketchPlan& sp,
+                         hipStream_t st) {
+    if (out_f64) {
+        switch (dtype) {
+            case 0: return sketch_type<double, double>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
+            case 1: return sketch_type<float, double>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
+            case 2: return sketch_type<bf16_t, double>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
+        }
+    } else {
+        switch (dtype) {
+            case 0: return sketch_type<double, float>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
+            case 1: return sketch_type<float, float>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
+            case 2: return sketch_type<bf16_t, float>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_btg(const void* B, int b_f64, int m, int w, const double* g, double* u, hipStream_t st) {
+    hipError_t e = launch_fill(u, w, 0.0, st);
+    if (e != hipSuccess) return e;
+    const int bx = (w + 255) / 256;
+    int chunks = (512 + bx - 1) / bx;
+    int rpc = (m + chunks - 1) / chunks;
+    if (rpc < 16) rpc = 16;
+    chunks = (m + rpc - 1) / rpc;
+    if (b_f64)
+        hipLaunchKernelGGL(k_btg<double>, dim3(bx, chunks), dim3(256), 0, st, reinterpret_cast<const double*>(B), m, w,
+                           rpc, g, u);
+    else
+        hipLaunchKernelGGL(k_btg<float>, dim3(bx, chunks), dim3(256), 0, st, reinterpret_cast<const float*>(B), m, w,
+                           rpc, g, u);
+    return hipGetLastError();
+}
+
+int pointwise_blocks(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_dx(int64_t n, const double* x, const double* s, const double* d2, const double* ds,
+                     const double* u, int vcorr, const HashKeys& hk, const double* scal, double* dx, double* part3,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_dx, dim3(pointwise_blocks(n)), dim3(256), 0, st, n, x, s, d2, ds, u, vcorr, hk, scal, dx,
+                       part3);
+    return hipGetLastError();
+}
+
+}  // namespace ipmsk

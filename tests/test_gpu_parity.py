@@ -1,0 +1,286 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle on the same seeded inputs.
+
+Every comparison is element by element against the oracle or, for the LP optimum, against
+quantities the oracle tests pin independently. Tolerances are stated per test with the
+reason.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import lpgen
+from oracle import ipm as oipm
+from oracle import sketch as osk
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P = None
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    global P
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2209_08722_amd as mod
+    P = mod
+    c = mod.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rand_lp_matrix(m, n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((m, n))
+
+
+# ------------------------------------------------------------------------- matvec pass
+
+@pytest.mark.parametrize("m,n", [(1, 100), (7, 33), (50, 2000), (37, 1001), (130, 5003), (500, 20011),
+                                 (257, 4096), (1000, 3000)])
+def test_normal_matvec_fp64(ctx, m, n):
+    A = rand_lp_matrix(m, n, m * 7 + n)
+    rng = np.random.default_rng(1)
+    d2 = np.exp(rng.uniform(-6, 6, n))
+    v = rng.standard_normal(m)
+    q = host(P.ipm_normal_matvec(ctx, P.Matrix.from_numpy(A), dev(d2), dev(v)))
+    ref = A @ (d2 * (A.T @ v))
+    # FP64 summation bound: |error| <= c * eps * |A| (d2 * |A|^T |v|) with c ~ m + n
+    bound = np.abs(A) @ (d2 * (np.abs(A).T @ np.abs(v)))
+    assert np.all(np.abs(q - ref) <= 64 * np.finfo(float).eps * (m + np.sqrt(n)) * bound + 1e-300)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_normal_matvec_low_storage(ctx, dtype):
+    m, n = 60, 3001
+    A = rand_lp_matrix(m, n, 5)
+    A = lpgen.bf16_round(A) if dtype == "bf16" else lpgen.f32_round(A)
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    rng = np.random.default_rng(2)
+    d2 = np.exp(rng.uniform(-3, 3, n))
+    v = rng.standard_normal(m)
+    q = host(P.ipm_normal_matvec(ctx, P.Matrix.from_numpy(A, dtype=tdt), dev(d2), dev(v)))
+    ref = A @ (d2 * (A.T @ v))
+    bound = np.abs(A) @ (d2 * (np.abs(A).T @ np.abs(v)))
+    # storage is exact (values are representable); accumulation is FP64
+    assert np.all(np.abs(q - ref) <= 64 * np.finfo(float).eps * (m + np.sqrt(n)) * bound)
+
+
+# ------------------------------------------------------------------------- sketch
+
+@pytest.mark.parametrize("m,n,w,s,seed,k", [(50, 2000, 200, 1, 0, 0), (37, 1001, 96, 3, 5, 7),
+                                            (5, 40, 12, 3, 11, 4), (64, 5000, 256, 8, 2, 1),
+                                            (500, 20000, 2000, 2, 9, 3), (3, 17, 4, 2, 1, 0)])
+def test_sketch_parity(ctx, m, n, w, s, seed, k):
+    A = rand_lp_matrix(m, n, 100 + m)
+    rng = np.random.default_rng(3)
+    d = np.exp(rng.uniform(-2, 2, n))
+    B = host(P.ipm_sketch(ctx, P.Matrix.from_numpy(A), dev(d), seed, k, w, s))
+    ref = osk.sketch_ADW(A, d, w, s, seed, k)
+    # each bucket sums ~ n*s/w terms; only the summation order differs
+    W = osk.sketch_matrix(n, w, s, seed, k)
+    bound = np.asarray((abs(W).T @ (np.abs(A) * d).T).T)
+    assert np.all(np.abs(B - ref) <= 32 * np.finfo(float).eps * np.sqrt(n) * bound + 1e-300)
+
+
+def test_sketch_fp32_output(ctx):
+    m, n, w, s = 40, 3000, 160, 2
+    A = rand_lp_matrix(m, n, 8)
+    d = np.exp(np.random.default_rng(4).uniform(-1, 1, n))
+    B = host(P.ipm_sketch(ctx, P.Matrix.from_numpy(A), dev(d), 3, 2, w, s, out_dtype=torch.float32))
+    ref = osk.sketch_ADW(A, d, w, s, 3, 2)
+    assert np.max(np.abs(B - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------------------------- factor
+
+@pytest.mark.parametrize("m,w", [(1, 4), (50, 200), (64, 128), (65, 130), (130, 520), (200, 400), (500, 2000)])
+def test_precond_factor(ctx, m, w):
+    rng = np.random.default_rng(m)
+    B = rng.standard_normal((m, w)) * np.exp(rng.uniform(-2, 2, (m, 1)))
+    L, Linv = P.ipm_precond_factor(ctx, dev(B))
+    L, Linv = np.tril(host(L)), host(Linv)
+    Q = B @ B.T
+    Lref = np.linalg.cholesky(Q)
+    kap = np.linalg.cond(Lref)
+    assert np.linalg.norm(L - Lref) <= 1e-13 * kap * np.linalg.norm(Lref)
+    assert np.allclose(np.triu(Linv, 1), 0.0)
+    assert np.linalg.norm(Linv @ Lref - np.eye(m)) <= 1e-13 * kap * kap * np.sqrt(m)
+
+
+def test_precond_factor_reports_bad_pivot(ctx):
+    rng = np.random.default_rng(0)
+    B = rng.standard_normal((80, 160))
+    B[17] = 0.0
+    with pytest.raises(P.IpmError) as ei:
+        P.ipm_precond_factor(ctx, dev(B))
+    assert ei.value.code == -3
+
+
+# ------------------------------------------------------------------------- PCG
+
+def _pcg_case(m=50, n=2000, w=200, s=2, seed=0):
+    A = rand_lp_matrix(m, n, 31)
+    rng = np.random.default_rng(seed)
+    d2 = np.exp(rng.uniform(-5, 5, n))
+    B = osk.sketch_ADW(A, np.sqrt(d2), w, s, seed, 0)
+    L = np.linalg.cholesky(B @ B.T)
+    p = rng.standard_normal(m)
+    return A, d2, L, p
+
+
+@pytest.mark.parametrize("maxit", [500, 1, 3])
+def test_pcg_parity(ctx, maxit):
+    A, d2, L, p = _pcg_case()
+    Linv = np.linalg.inv(L)
+    prm = P.Params(w=200, s=2, maxit_pcg=maxit)
+    dy, info = P.ipm_pcg_solve(ctx, P.Matrix.from_numpy(A), dev(d2), dev(np.tril(Linv)), dev(p), prm)
+    dy = host(dy)
+    M = (A * d2) @ A.T
+    ref = oipm.pcg(lambda v: M @ v, L, p, 1e-10, maxit)
+    assert abs(info["iters"] - ref.iters) <= 1
+    if maxit < 10:
+        assert info["iters"] == ref.iters
+        assert info["status"] == 2
+    e = dy - ref.dy
+    en = np.sqrt(e @ M @ e) / np.sqrt(ref.dy @ M @ ref.dy)
+    assert en <= (1e-8 if maxit >= 10 else 1e-12)
+    # the paper's residual ||Q^{-1/2}(M dy - p)|| recomputed by the oracle
+    f = sla.solve_triangular(L, M @ dy - p, lower=True)
+    fp = sla.solve_triangular(L, p, lower=True)
+    if maxit >= 10:
+        assert np.linalg.norm(f) <= 1e-10 * np.linalg.norm(fp) * 1.01 + 1e-12 * np.linalg.norm(fp)
+
+
+def test_pcg_warm_start(ctx):
+    A, d2, L, p = _pcg_case(seed=4)
+    Linv = np.tril(np.linalg.inv(L))
+    M = (A * d2) @ A.T
+    xs = np.linalg.solve(M, p)
+    prm = P.Params(w=200, s=2)
+    good = xs * (1 + 1e-4 * np.random.default_rng(0).standard_normal(xs.size))
+    dy_w, info_w = P.ipm_pcg_solve(ctx, P.Matrix.from_numpy(A), dev(d2), dev(Linv), dev(p), prm, dy0=dev(good))
+    _, info_c = P.ipm_pcg_solve(ctx, P.Matrix.from_numpy(A), dev(d2), dev(Linv), dev(p), prm)
+    assert info_w["warm_used"] == 1 and info_w["iters"] < info_c["iters"]
+    ref = oipm.pcg(lambda v: M @ v, L, p, 1e-10, 500, dy0=good)
+    assert abs(info_w["iters"] - ref.iters) <= 1
+    bad = -1e3 * xs
+    _, info_b = P.ipm_pcg_solve(ctx, P.Matrix.from_numpy(A), dev(d2), dev(Linv), dev(p), prm, dy0=dev(bad))
+    assert info_b["warm_used"] == 0 and abs(info_b["iters"] - info_c["iters"]) <= 1
+
+
+# ------------------------------------------------------------------------- IPM step and solve
+
+def _gpu_state(st):
+    return P.State(dev(st.x), dev(st.y), dev(st.s), st.k, st.mu0, st.r0norm)
+
+
+def _lockstep(ctx, lp, oprm, gprm, steps, rtol_state):
+    prob = P.Problem.from_lp(lp)
+    st = oipm.initial_state(lp.A, lp.b, lp.c)
+    for k in range(steps):
+        gst = _gpu_state(st)
+        ginfo = P.ipm_step(ctx, prob, gst, gprm)
+        new, oinfo = oipm.step(lp.A, lp.b, lp.c, st, oprm, "sketch")
+        assert oinfo.status >= 0 and ginfo["rc"] >= 0
+        for key in ("mu", "relgap", "rp_rel", "rd_rel"):
+            assert ginfo[key] == pytest.approx(getattr(oinfo, key), rel=1e-11, abs=1e-15)
+        if oinfo.status == oipm.CONVERGED:
+            assert ginfo["rc"] == 1
+            return k
+        # CG in finite precision: counts may drift by a few iterations once the preconditioned
+        # system is ill-conditioned (different summation order, explicit L^{-1}); both sides
+        # meet the same residual tolerance, which the state comparison below checks.
+        assert abs(ginfo["pcg_iters"] - oinfo.pcg_iters) <= max(1, 0.1 * oinfo.pcg_iters)
+        assert ginfo["pcg_relres"] <= oprm.tol_pcg or ginfo["pcg_status"] > 0
+        assert ginfo["attempts"] == oinfo.extra.get("attempts", 1)
+        assert ginfo["alpha"] == pytest.approx(oinfo.alpha, rel=1e-7, abs=1e-10)
+        for name in ("x", "y", "s"):
+            g = host(getattr(gst, name))
+            o = getattr(new, name)
+            assert np.linalg.norm(g - o) <= rtol_state * (np.linalg.norm(o) + 1e-300), (k, name)
+        st = new
+    return steps
+
+
+def test_step_lockstep_config0(ctx):
+    lp = lpgen.config(0)
+    oprm = oipm.Params(w=200, s=1, seed=0)
+    _lockstep(ctx, lp, oprm, P.Params(w=200, s=1, seed=0), steps=12, rtol_state=1e-8)
+
+
+def test_step_lockstep_ragged(ctx):
+    lp = lpgen.dense_lp(23, 1003, seed=5)
+    oprm = oipm.Params(w=92, s=2, seed=7)
+    _lockstep(ctx, lp, oprm, P.Params(w=92, s=2, seed=7), steps=10, rtol_state=1e-8)
+
+
+def test_solve_config0_matches_oracle(ctx):
+    lp = lpgen.config(0)
+    res = P.solve(ctx, P.Problem.from_lp(lp), P.Params(w=200, s=1, seed=0))
+    ores = oipm.solve(lp.A, lp.b, lp.c, oipm.Params(w=200, s=1, seed=0), "sketch")
+    assert res.converged and ores.converged
+    assert abs(res.iterations - len(ores.infos) + 1) <= 1
+    x = host(res.state.x)
+    obj = float(lp.c @ x)
+    oobj = float(lp.c @ ores.state.x)
+    assert abs(obj - oobj) <= 1e-8 * (1 + abs(oobj))
+    last = res.infos[-1]
+    assert max(last["relgap"], last["rp_rel"], last["rd_rel"]) <= 1e-8
+    assert np.linalg.norm(x - ores.state.x) <= 1e-5 * np.linalg.norm(ores.state.x)
+
+
+@pytest.mark.parametrize("m,n,w,s", [(1, 50, 4, 2), (6, 6, 24, 2), (4, 11, 8, 1), (20, 2000, 2000, 8)])
+def test_solve_edge_shapes(ctx, m, n, w, s):
+    if m == 1:
+        rng = np.random.default_rng(6)
+        a = rng.uniform(0.5, 2.0, n)
+        c = rng.uniform(0.1, 3.0, n)
+        A, b = a[None, :], np.array([3.0])
+        lp = lpgen.LP(A, b, c, None, None, None)
+        opt = 3.0 * np.min(c / a)
+    else:
+        lp = lpgen.dense_lp(m, n, seed=m + n)
+        ores = oipm.solve(lp.A, lp.b, lp.c, oipm.Params(w=w, s=s), "exact")
+        opt = float(lp.c @ ores.state.x)
+    res = P.solve(ctx, P.Problem.from_lp(lp), P.Params(w=w, s=s))
+    assert res.converged
+    obj = float(lp.c @ host(res.state.x))
+    assert abs(obj - opt) <= 1e-7 * (1 + abs(opt))
+
+
+def test_argument_errors(ctx):
+    lp = lpgen.dense_lp(10, 100, seed=1)
+    prob = P.Problem.from_lp(lp)
+    for bad in (P.Params(w=8, s=2), P.Params(w=30, s=4), P.Params(w=40, s=9)):
+        st = P.State.initial(10, 100)
+        with pytest.raises(P.IpmError) as ei:
+            P.ipm_step(ctx, prob, st, bad)
+        assert ei.value.code == -1
+        assert float(st.x.sum()) == 100.0   # untouched
+
+
+def test_config1_full_size_lockstep_and_solve(ctx):
+    """The bench workload (500 x 100000, w = 2000, s = 2): two lockstep steps against the
+    oracle, then the full GPU solve against the oracle's direct-solver IPM optimum."""
+    lp = lpgen.config(1, seed=0)
+    oprm = oipm.Params(w=2000, s=2, seed=0)
+    _lockstep(ctx, lp, oprm, P.Params(w=2000, s=2, seed=0), steps=2, rtol_state=1e-9)
+    res = P.solve(ctx, P.Problem.from_lp(lp), P.Params(w=2000, s=2, seed=0))
+    assert res.converged
+    ores = oipm.solve(lp.A, lp.b, lp.c, oipm.Params(), "exact")
+    assert ores.converged
+    obj = float(lp.c @ host(res.state.x))
+    oobj = float(lp.c @ ores.state.x)
+    assert abs(obj - oobj) <= 1e-8 * (1 + abs(oobj))
+    assert abs(res.iterations - (len(ores.infos) - 1)) <= 2
