@@ -89,6 +89,8 @@ def main() -> int:
     ap.add_argument("--workload", default="1", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -96,6 +98,15 @@ def main() -> int:
         return 2
 
     import torch
+    if args.calibrate_copy:
+        nel = args.calibrate_copy // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {nel * 8} bytes")
+        return 0
     import lpgen
     import paper_2209_08722_amd as P
 
