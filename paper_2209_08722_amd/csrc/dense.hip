@@ -98,46 +98,71 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
 
 // Factor the kb x kb diagonal block at (k0, k0) of the partially updated matrix in place
 // (lower triangle) and write its inverse into X's diagonal block (zero above the diagonal).
-// One wave; the block lives in LDS. A pivot that is not positive is recorded in *status
-// (smallest index wins) and replaced by 1 so the remaining work stays finite.
+// One wave. Lane t keeps row t of the block in registers during the factorization (right-looking:
+// the scaled column c is shared through LDS) and column t of the inverse during the forward
+// substitution X L = I (rows of L broadcast from LDS). Loops are fully unrolled so the row and
+// column arrays stay in registers. A pivot that is not positive is recorded in *status (smallest
+// index wins) and replaced by 1 so the remaining work stays finite.
 __global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ Lw, int64_t ld, int k0, int kb,
                                                    double* __restrict__ X, int64_t ldx, int* __restrict__ status) {
-    __shared__ double a[64][65];
-    __shared__ double xi[64][65];
+    __shared__ double col[64];
+    __shared__ double Ls[64][65];
     const int t = threadIdx.x;
-    for (int i = 0; i < kb; ++i) a[i][t] = (t <= i) ? Lw[(int64_t)(k0 + i) * ld + k0 + t] : 0.0;
-    __syncthreads();
-    for (int c = 0; c < kb; ++c) {
-        double piv = a[c][c];
-        __syncthreads();
-        if (!(piv > 0.0)) {
-            if (t == 0) atomicMin(status, k0 + c);
-            piv = 1.0;
+    double r[64];
+    const double* src = Lw + (int64_t)(k0 + (t < kb ? t : 0)) * ld + k0;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) r[j] = (t < kb && j <= t) ? src[j] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+        if (c < kb) {
+            double piv = __shfl(r[c], c, 64);
+            if (!(piv > 0.0)) {
+                if (t == 0) atomicMin(status, k0 + c);
+                piv = 1.0;
+            }
+            const double lcc = sqrt(piv);
+            const double inv = 1.0 / lcc;
+            if (t == c) r[c] = lcc;
+            else if (t > c) r[c] *= inv;
+            col[t] = r[c];
+            __syncthreads();
+            const double ltc = r[c];
+#pragma unroll
+            for (int j = c + 1; j < 64; ++j) {
+                const double ljc = col[j];
+                if (t > c && j <= t) r[j] -= ltc * ljc;
+            }
+            __syncthreads();
         }
-        const double lcc = sqrt(piv);
-        if (t == c) a[c][c] = lcc;
-        if (t > c && t < kb) a[t][c] = a[t][c] / lcc;
-        __syncthreads();
-        if (t > c && t < kb) {
-            const double lic = a[t][c];
-            for (int j = c + 1; j <= t; ++j) a[t][j] -= lic * a[j][c];
-        }
-        __syncthreads();
     }
-    for (int i = 0; i < kb; ++i)
-        if (t <= i) Lw[(int64_t)(k0 + i) * ld + k0 + t] = a[i][t];
+    // row t of L to LDS (for the inverse) and back to global memory
+#pragma unroll
+    for (int j = 0; j < 64; ++j) Ls[t][j] = r[j];
     if (t < kb) {
-        for (int i = 0; i < t; ++i) xi[i][t] = 0.0;
-        xi[t][t] = 1.0 / a[t][t];
-        for (int i = t + 1; i < kb; ++i) {
-            double s = 0.0;
-            for (int q = t; q < i; ++q) s += a[i][q] * xi[q][t];
-            xi[i][t] = -s / a[i][i];
-        }
+        double* dst = Lw + (int64_t)(k0 + t) * ld + k0;
+#pragma unroll
+        for (int j = 0; j < 64; ++j)
+            if (j <= t) dst[j] = r[j];
     }
     __syncthreads();
-    for (int i = 0; i < kb; ++i)
-        if (t < kb) X[(int64_t)(k0 + i) * ldx + k0 + t] = xi[i][t];
+    // column t of X = L^{-1}: X[i][t] = (delta_it - sum_{q<i} L[i][q] X[q][t]) / L[i][i]
+    double x[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        if (i < kb) {
+            double s = (i == t) ? 1.0 : 0.0;
+#pragma unroll
+            for (int q = 0; q < i; ++q) s -= Ls[i][q] * x[q];
+            x[i] = s / Ls[i][i];
+        } else {
+            x[i] = 0.0;
+        }
+    }
+    if (t < kb) {
+#pragma unroll
+        for (int i = 0; i < 64; ++i)
+            if (i < kb) X[(int64_t)(k0 + i) * ldx + k0 + t] = x[i];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ X, double* __restrict__ XT, int m) {

@@ -18,7 +18,7 @@ namespace {
 enum WsId {
     W_PART = 0, W_COLPART, W_RED, W_D2, W_RD, W_DS, W_DX, W_RP, W_P, W_DY, W_RHAT, W_G1, W_G2, W_U, W_B,
     W_L, W_X, W_XT, W_T, W_SCAL, W_PCG_VEC, W_PCG_RHO, W_PCG_CD, W_PCG_CI, W_STATUS, W_PART3, W_PARTMIN,
-    W_INFO, W_DQ, W_COUNT
+    W_INFO, W_GPART, W_SQ, W_COUNT
 };
 
 struct TimedPair {
@@ -41,6 +41,7 @@ struct ipm_ctx {
     double total_ms[IPM_KERNEL_COUNT] = {};
     int64_t launches[IPM_KERNEL_COUNT] = {};
     std::vector<hipEvent_t> pool;
+    int last_pcg_iters = 8;    // size of the first batch of queued CG iterations
 };
 
 namespace {
@@ -252,24 +253,35 @@ int do_factor(ipm_ctx* ctx, int m, int w, int b_f64, const void* B, double* Lw, 
     return IPM_OK;
 }
 
-// One matvec pass over A: part <- partials of A diag(d2) A^T v.
-int matvec_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v, double* part,
+// Workspace of a strip pass with `nacc` row accumulators (per-block partials and sums).
+int strip_buffers(ipm_ctx* ctx, const StripPlan& pl, int m, int nacc, StripCall* c) {
+    CHK(ws(ctx, W_PART, (size_t)nacc * pl.grid * m, &c->part));
+    CHK(ws(ctx, W_COLPART, (size_t)pl.grid, &c->colpart));
+    CHK(ws(ctx, W_GPART, (size_t)rowsum_blocks(m), &c->gpart));
+    return IPM_OK;
+}
+
+// One matvec pass over A: out <- A diag(d2) A^T v.
+int matvec_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v, double* out,
                 const StripPlan& pl, const int* done, int tag) {
     StripCall c{};
     c.kind = STRIP_MATVEC;
     c.dtype = A->dtype;
     c.acc64 = 1;
+    c.post = POST_PLAIN;
     c.A = A->val;
     c.m = (int)A->m;
     c.n = A->n;
     c.ld = A->ld;
     c.vec0 = v;
     c.d2 = d2;
-    c.part = part;
+    c.out0 = out;
     c.done = done;
+    CHK(strip_buffers(ctx, pl, c.m, 1, &c));
     Timer t(ctx, IPM_KERNEL_MATVEC, tag);
-    HIPCHK(launch_strip(c, pl, ctx->stream));
+    HIPCHK(launch_strip_pass(c, pl, ctx->stream));
     t.stop();
+    HIPCHK(launch_strip_rowsum(c, pl, ctx->stream));
     return IPM_OK;
 }
 
@@ -288,16 +300,13 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     HIPCHK(launch_transpose(X, XT, m, st));
     const StripPlan pl = strip_plan(A->dtype, m, A->n, ctx->num_cu, STRIP_MATVEC);
     if (pl.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
-    double *part = nullptr, *vec = nullptr, *rho = nullptr, *cd = nullptr, *dq = nullptr, *info = nullptr;
+    double *vec = nullptr, *rho = nullptr, *cd = nullptr, *info = nullptr;
     int* ci = nullptr;
-    CHK(ws(ctx, W_PART, (size_t)pl.grid * m, &part));
     CHK(ws(ctx, W_PCG_VEC, (size_t)8 * m, &vec));
     const int gb = gemv_blocks(m);
     CHK(ws(ctx, W_PCG_RHO, (size_t)2 * gb, &rho));
     CHK(ws(ctx, W_PCG_CD, (size_t)PD_HIST + prm->maxit_pcg + 2, &cd));
     CHK(ws(ctx, W_PCG_CI, PI_COUNT, &ci));
-    const int nred = reduce_rows_blocks(m);
-    CHK(ws(ctx, W_DQ, (size_t)nred, &dq));
     CHK(ws(ctx, W_INFO, 8, &info));
     PcgBufs b{};
     b.m = m;
@@ -312,8 +321,6 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     b.q = vec + 5 * m;
     b.wv = vec + 6 * m;
     b.wv2 = vec + 7 * m;
-    b.dq_part = dq;
-    b.n_dq = nred;
     b.rho_part = rho;
     b.n_rho = gb;
     b.cd = cd;
@@ -323,22 +330,18 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     b.stag_window = prm->stag_window;
     b.maxit = prm->maxit_pcg;
     HIPCHK(launch_fill_i32(ci, PI_COUNT, 0, st));
-    if (warm) {
-        CHK(matvec_pass(ctx, A, d2, dy_out, part, pl, nullptr, -1));
-        HIPCHK(launch_reduce_rows(POST_PLAIN, part, pl.grid, m, 1, nullptr, nullptr, nullptr, b.q, nullptr, nullptr,
-                                  nullptr, st));
-    }
+    if (warm) CHK(matvec_pass(ctx, A, d2, dy_out, b.q, pl, nullptr, -1));
     HIPCHK(launch_pcg_init1(b, warm, st));
     HIPCHK(launch_pcg_init2(b, warm, dy_out, st));
     int* hi = reinterpret_cast<int*>(ctx->pinned);
     int j = 0;
-    int batch = 8;
+    // first batch: the previous solve's iteration count (CG counts change slowly between IPM
+    // iterations); later batches are short so that few no-op launches follow the stop
+    int batch = ctx->last_pcg_iters > 4 ? ctx->last_pcg_iters : 4;
     const int* done = ci + PI_DONE;
     for (;;) {
         for (int t = 0; t < batch && j < prm->maxit_pcg; ++t, ++j) {
-            CHK(matvec_pass(ctx, A, d2, b.dv, part, pl, done, j));
-            HIPCHK(launch_reduce_rows(POST_MATVEC, part, pl.grid, m, 1, nullptr, nullptr, b.dv, b.q, nullptr, dq, done,
-                                      st));
+            CHK(matvec_pass(ctx, A, d2, b.dv, b.q, pl, done, j));
             HIPCHK(launch_pcg_gemv1(b, j, st));
             HIPCHK(launch_pcg_gemv2(b, j, st));
         }
@@ -356,6 +359,7 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     out->warm_used = (int)hd[2];
     out->relres = hd[3];
     out->rho_star = hd[4];
+    ctx->last_pcg_iters = out->iters;
     resolve_timing(ctx, IPM_KERNEL_MATVEC, out->iters);
     resolve_timing(ctx, IPM_KERNEL_SKETCH, INT_MAX);
     return IPM_OK;
@@ -422,6 +426,7 @@ int ipm_ctx_create(ipm_ctx** out, int device, void* hip_stream) {
         delete ctx;
         return IPM_ERR_HIP;
     }
+
     *out = ctx;
     return IPM_OK;
 }
@@ -527,11 +532,7 @@ int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const
     const int m = (int)A->m;
     const StripPlan pl = strip_plan(A->dtype, m, A->n, ctx->num_cu, STRIP_MATVEC);
     if (pl.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
-    double* part = nullptr;
-    CHK(ws(ctx, W_PART, (size_t)pl.grid * m, &part));
-    CHK(matvec_pass(ctx, A, d2, v, part, pl, nullptr, -1));
-    HIPCHK(launch_reduce_rows(POST_PLAIN, part, pl.grid, m, 1, nullptr, nullptr, nullptr, q, nullptr, nullptr, nullptr,
-                              ctx->stream));
+    CHK(matvec_pass(ctx, A, d2, v, q, pl, nullptr, -1));
     return IPM_OK;
 }
 
@@ -549,7 +550,7 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
     const int64_t n = A->n;
     const int Gn = pointwise_blocks(n);
 
-    double *d2, *rd, *ds, *dx, *rp, *p, *dyv, *rhat, *g1, *g2, *scal, *part3, *partmin, *colpart, *rp2part, *part;
+    double *d2, *rd, *ds, *dx, *rp, *p, *dyv, *rhat, *g1, *g2, *scal, *part3, *partmin, *sq;
     CHK(ws(ctx, W_D2, n, &d2));
     CHK(ws(ctx, W_RD, n, &rd));
     CHK(ws(ctx, W_DS, n, &ds));
@@ -565,10 +566,7 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
     CHK(ws(ctx, W_PARTMIN, Gn, &partmin));
     const StripPlan plr = strip_plan(IPM_F64 == A->dtype ? IPM_F64 : A->dtype, m, n, ctx->num_cu, STRIP_RESID);
     if (plr.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
-    CHK(ws(ctx, W_COLPART, plr.grid, &colpart));
-    const int nred = reduce_rows_blocks(m);
-    CHK(ws(ctx, W_RED, nred, &rp2part));
-    CHK(ws(ctx, W_PART, (size_t)2 * plr.grid * m, &part));
+    CHK(ws(ctx, W_SQ, 4, &sq));
 
     // residuals, mu, p and the stop test at the current point (Algorithm 3, step 3)
     HIPCHK(launch_stats(n, state->x, state->s, prob->c, d2, part3, st));
@@ -589,13 +587,17 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
         c.c = prob->c;
         c.rd_out = rd;
         c.scal = scal;
-        c.part = part;
-        c.colpart = colpart;
+        c.post = POST_RESID;
+        c.b = prob->b;
+        c.out0 = rp;
+        c.out1 = p;
+        c.outsc = sq;
+        CHK(strip_buffers(ctx, plr, m, 2, &c));
         HIPCHK(launch_strip(c, plr, st));
     }
-    HIPCHK(launch_reduce_rows(POST_RESID, part, plr.grid, m, 2, prob->b, nullptr, nullptr, rp, p, rp2part, nullptr, st));
     const int set_ref = state->r0norm < 0.0 ? 1 : 0;
-    HIPCHK(launch_metrics(n, m, rp2part, nred, colpart, plr.grid, set_ref, state->mu0, state->r0norm, scal, st));
+    HIPCHK(launch_metrics(n, m, ctx->ws[W_GPART] ? reinterpret_cast<double*>(ctx->ws[W_GPART]) : nullptr,
+                          rowsum_blocks(m), sq + 1, set_ref, state->mu0, state->r0norm, scal, st));
     double* hs = reinterpret_cast<double*>(ctx->pinned);
     HIPCHK(hipMemcpyAsync(hs, scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -673,10 +675,11 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
         c.d2 = d2;
         c.rd = rd;
         c.ds_out = ds;
-        c.part = part;
+        c.post = POST_RHAT;
+        c.pvec = p;
+        c.out0 = rhat;
+        CHK(strip_buffers(ctx, pld, m, 1, &c));
         HIPCHK(launch_strip(c, pld, st));
-        HIPCHK(launch_reduce_rows(POST_RHAT, part, pld.grid, m, 1, nullptr, p, nullptr, rhat, nullptr, nullptr, nullptr,
-                                  st));
     }
     double* u = nullptr;
     CHK(ws(ctx, W_U, (size_t)wmax, &u));

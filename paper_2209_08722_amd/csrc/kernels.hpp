@@ -27,11 +27,13 @@ struct StripPlan {
     size_t lds;    // dynamic LDS bytes
 };
 
-// Arguments of every strip pass. Unused pointers may be null.
+// Arguments of every strip pass. Unused pointers may be null. launch_strip queues the pass and
+// the row reduction of its per-block partials (which applies the RowPost step).
 struct StripCall {
     int kind;
     int dtype;               // IPM_F64 / IPM_F32 / IPM_BF16
     int acc64;               // 1: FP64 accumulation, 0: FP32 (mixed-precision matvec)
+    int post;                // RowPost
     const void* A;
     int m;
     int64_t n, ld;
@@ -44,21 +46,24 @@ struct StripCall {
     double* rd_out;          // n (resid: output r_d)
     double* ds_out;          // n (dir: output ds)
     const double* scal;      // device scalar block (resid reads SC_SMU)
-    double* part;            // [nacc][grid][m] partial row sums
-    double* colpart;         // [grid] partial per-column reductions (resid: sum r_d^2)
+    const double* b;         // m (resid post)
+    const double* pvec;      // m (rhat post)
+    const double* dvec;      // m (matvec post: d^T q)
+    double* out0;            // m outputs of the post step
+    double* out1;
+    double* outsc;           // resid post: [1] = ||r_d||^2
+    double* part;            // [nacc][m][grid] per-block partial row sums
+    double* colpart;         // [grid] per-block column reductions (resid: sum of r_d^2)
+    double* gpart;           // resid post: per-reduction-block sums of r_p^2 [rowsum_blocks(m)]
     const int* done;         // early-exit flag (may be null)
 };
 
 StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind);
-hipError_t launch_strip(const StripCall& c, const StripPlan& p, hipStream_t st);
-
-// Row reduction of partials: out0/out1 as described by RowPost; blockpart gets per-block sums
-// (matvec: d^T q with d = dvec; resid: ||r_p||^2). Returns the number of blocks used.
-int reduce_rows_blocks(int m);
-hipError_t launch_reduce_rows(int post, const double* part, int G, int m, int nacc,
-                              const double* b, const double* pvec, const double* dvec,
-                              double* out0, double* out1, double* blockpart, const int* done,
-                              hipStream_t st);
+hipError_t launch_strip(const StripCall& c, const StripPlan& p, hipStream_t st);   // pass + rowsum
+hipError_t launch_strip_pass(const StripCall& c, const StripPlan& p, hipStream_t st);
+hipError_t launch_strip_rowsum(const StripCall& c, const StripPlan& p, hipStream_t st);
+int rowsum_blocks(int m);
+constexpr int kStripMaxGrid = 4096;
 
 // ---- sketch and perturbation -----------------------------------------------------------------
 struct SketchPlan { int rows_per_block; int chunks; int64_t cols_per_chunk; size_t lds; bool atomic; bool global_only; };
@@ -103,8 +108,6 @@ struct PcgBufs {
     double* q;            // A D^2 A^T dv
     double* wv;           // L^{-1} r
     double* wv2;          // second right-hand side (warm start)
-    const double* dq_part;
-    int n_dq;
     double* rho_part;
     int n_rho;
     double* cd;           // PcgDbl block (hist at PD_HIST)
@@ -128,8 +131,8 @@ hipError_t launch_stats(int64_t n, const double* x, const double* s, const doubl
                         double* part3, hipStream_t st);
 hipError_t launch_fin_stats(int64_t n, int m, const double* part3, int G, const double* b, const double* y,
                             double sigma, double* scal, hipStream_t st);
-hipError_t launch_metrics(int64_t n, int m, const double* rp2part, int Grp, const double* rd2part, int Grd,
-                          int set_ref, double mu0_in, double r0_in, double* scal, hipStream_t st);
+hipError_t launch_metrics(int64_t n, int m, const double* rp2part, int Grp, const double* rd2, int set_ref,
+                          double mu0_in, double r0_in, double* scal, hipStream_t st);
 hipError_t launch_fin_dx(const double* part3, int G, double* scal, hipStream_t st);
 hipError_t launch_roots(int64_t n, const double* x, const double* s, const double* dx, const double* ds,
                         double gamma, const double* scal, double* partmin, hipStream_t st);

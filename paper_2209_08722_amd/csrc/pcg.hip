@@ -6,8 +6,8 @@
 // which is the CG scalar rho = r^T z.
 //
 // All CG scalars live on the device. One iteration is four launches:
-//   matvec pass (strip kernel) -> row reduction (q = A D^2 A^T d and partial d^T q)
-//   -> gemv1: alpha, dy += alpha d, r -= alpha q, w = X r, partial ||w||^2
+//   matvec pass (strip kernel, then the row reduction of its per-block partials: q = A D^2 A^T d)
+//   -> gemv1: d^T q, alpha, dy += alpha d, r -= alpha q, w = X r, partial ||w||^2
 //   -> gemv2: rho', beta, d = X^T w + beta d, stop tests.
 // A device flag ends the iteration; kernels of later, already queued iterations return at once,
 // so the host queues iterations in batches and reads the flag once per batch. dy and r are
@@ -98,7 +98,9 @@ __global__ __launch_bounds__(GNT) void k_pcg_gemv1(PcgBufs b, int j) {
     __shared__ double sh[GNW];
     const int m = b.m, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int par = j & 1;
-    const double dq = sum_partials(b.dq_part, b.n_dq, 1, sh);
+    double dqp = 0.0;
+    for (int l = tid; l < m; l += GNT) dqp += b.dv[l] * b.q[l];
+    const double dq = block_sum(dqp, sh);
     if (!(dq > 0.0)) {
         if (blockIdx.x == 0 && tid == 0) {
             b.ci[PI_STATUS] = -4;   // IPM_ERR_BREAKDOWN

@@ -56,11 +56,11 @@ __global__ __launch_bounds__(PNT) void k_fin_stats(int64_t n, int m, const doubl
 
 // Stop-test quantities at the current point; on the first call (set_ref) also mu0 and ||r0||.
 __global__ __launch_bounds__(PNT) void k_metrics(int64_t n, int m, const double* __restrict__ rp2part, int Grp,
-                                                 const double* __restrict__ rd2part, int Grd, int set_ref,
-                                                 double mu0_in, double r0_in, double* __restrict__ scal) {
+                                                 const double* __restrict__ rd2p, int set_ref, double mu0_in,
+                                                 double r0_in, double* __restrict__ scal) {
     __shared__ double sh[4];
     const double rp2 = sum_partials(rp2part, Grp, 1, sh);
-    const double rd2 = sum_partials(rd2part, Grd, 1, sh);
+    const double rd2 = *rd2p;
     if (threadIdx.x == 0) {
         const double ctx = scal[SC_CTX], bty = scal[SC_BTY];
         const double gap = ctx - bty;
@@ -190,10 +190,9 @@ hipError_t launch_fin_stats(int64_t n, int m, const double* part3, int G, const 
     return hipGetLastError();
 }
 
-hipError_t launch_metrics(int64_t n, int m, const double* rp2part, int Grp, const double* rd2part, int Grd,
-                          int set_ref, double mu0_in, double r0_in, double* scal, hipStream_t st) {
-    hipLaunchKernelGGL(k_metrics, dim3(1), dim3(PNT), 0, st, n, m, rp2part, Grp, rd2part, Grd, set_ref, mu0_in, r0_in,
-                       scal);
+hipError_t launch_metrics(int64_t n, int m, const double* rp2part, int Grp, const double* rd2, int set_ref,
+                          double mu0_in, double r0_in, double* scal, hipStream_t st) {
+    hipLaunchKernelGGL(k_metrics, dim3(1), dim3(PNT), 0, st, n, m, rp2part, Grp, rd2, set_ref, mu0_in, r0_in, scal);
     return hipGetLastError();
 }
 

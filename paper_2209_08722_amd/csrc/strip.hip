@@ -4,13 +4,17 @@
 // per-column coefficients; per row i: accumulate sum_j A[i][j] * coef_j". Reading A once per
 // pass requires each column strip to stay on chip between the dot and the accumulation, so a
 // block owns a strip of SW columns across all m rows, held in registers:
-//   - lanes: 8 lanes per row, 16-byte vector loads -> 128 contiguous bytes per row segment;
-//   - thread (c, g) holds rows g, g+RG, ... (RG = blockDim/8 row groups) of columns
+//   - lanes: LPR lanes per row, 16-byte vector loads -> LPR*16 contiguous bytes per row segment;
+//   - thread (c, g) holds rows g, g+RG, ... (RG = blockDim/LPR row groups) of columns
 //     [strip*SW + c*VEC, +VEC);
-//   - column dots: per-thread partials, then wave shuffles over the 8 row groups of a wave,
-//     then one LDS exchange across waves (double-buffered, one barrier per strip);
-//   - row sums: per-thread register accumulators, reduced over the 8 column lanes once at the
-//     end of the persistent loop and written as one partial m-vector per block.
+//   - column dots: per-thread partials, then wave shuffles over the row groups of a wave, then
+//     one LDS exchange across waves (double-buffered, one barrier per strip);
+//   - row sums: per-thread register accumulators, reduced over the column lanes once at the end
+//     of the persistent loop;
+//   - optionally the next strip's loads are issued before the current strip is reduced;
+//   - each block writes its partial row sums as part[acc][row][block]; a second kernel reduces
+//     them with one wave per row (coalesced over blocks) in a fixed order and applies the
+//     post-processing step (r_p, p, the true residual, ...).
 // The CG matvec q = A D^2 A^T v (Algorithm 1, step 3) is one such pass; so are the residual
 // pass (r_d = A^T y + s - c, then A x and A u for r_p and p, Section 5 / Algorithm 3 step 3) and
 // the direction pass (ds = -r_d - A^T dy, then A D^2 A^T dy for the true residual).
@@ -20,29 +24,29 @@ namespace ipmsk {
 
 namespace {
 
-constexpr int LPR = 8;   // lanes per row segment
+constexpr int kLpr = 8;      // lanes per row segment (8 x 16 B = 128 B)
 
 struct OpMatvec {
-    static constexpr int NDOT = 1, NACC = 1, NCR = 0;
+    static constexpr int NACC = 1, NCR = 0;
     struct S {};
     __device__ static S init(const StripCall&) { return {}; }
     template <typename ACC>
-    __device__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool,
-                                  const ACC* dots, ACC* coef, double*) {
-        coef[0] = valid ? (ACC)a.d2[j] * dots[0] : (ACC)0;
+    __device__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool, ACC dot, ACC* coef,
+                                  double*) {
+        coef[0] = valid ? (ACC)a.d2[j] * dot : (ACC)0;
     }
 };
 
 struct OpResid {
-    static constexpr int NDOT = 1, NACC = 2, NCR = 1;
+    static constexpr int NACC = 2, NCR = 1;
     struct S { double smu; };
     __device__ static S init(const StripCall& a) { return S{a.scal[SC_SMU]}; }
     template <typename ACC>
-    __device__ static void column(const StripCall& a, const S& st, int64_t j, bool valid, bool writer,
-                                  const ACC* dots, ACC* coef, double* cr) {
+    __device__ static void column(const StripCall& a, const S& st, int64_t j, bool valid, bool writer, ACC dot,
+                                  ACC* coef, double* cr) {
         if (!valid) { coef[0] = coef[1] = (ACC)0; return; }
         const double sj = a.s[j];
-        const double rdj = (double)dots[0] + sj - a.c[j];
+        const double rdj = (double)dot + sj - a.c[j];
         if (writer) { a.rd_out[j] = rdj; cr[0] += rdj * rdj; }
         coef[0] = (ACC)a.x[j];
         coef[1] = (ACC)(st.smu / sj + a.d2[j] * rdj);
@@ -50,43 +54,114 @@ struct OpResid {
 };
 
 struct OpDir {
-    static constexpr int NDOT = 1, NACC = 1, NCR = 0;
+    static constexpr int NACC = 1, NCR = 0;
     struct S {};
     __device__ static S init(const StripCall&) { return {}; }
     template <typename ACC>
-    __device__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool writer,
-                                  const ACC* dots, ACC* coef, double*) {
+    __device__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool writer, ACC dot,
+                                  ACC* coef, double*) {
         if (!valid) { coef[0] = (ACC)0; return; }
-        const double t = (double)dots[0];
+        const double t = (double)dot;
         if (writer) a.ds_out[j] = -a.rd[j] - t;
         coef[0] = (ACC)(a.d2[j] * t);
     }
 };
 
-template <typename T, typename ACC, int NT, int RPT, class Op>
+// Sum of the per-block partials part[acc][row][block] and the RowPost step: one wave per row.
+constexpr int RNT = 256;
+__global__ __launch_bounds__(RNT) void k_rowsum(StripCall a, int G, int nacc, int ncr) {
+    if (a.done != nullptr && *a.done) return;
+    __shared__ double shr[RNT / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int m = a.m;
+    const int i = blockIdx.x * (RNT / 64) + wid;
+    double contrib = 0.0;
+    if (i < m) {
+        double t0 = 0.0, t1 = 0.0;
+        const double* p0 = a.part + (int64_t)i * G;
+        const double* p1 = a.part + ((int64_t)m + i) * G;
+        for (int g = lane; g < G; g += 64) {
+            t0 += p0[g];
+            if (nacc > 1) t1 += p1[g];
+        }
+        t0 = wave_sum(t0);
+        if (nacc > 1) t1 = wave_sum(t1);
+        if (lane == 0) {
+            switch (a.post) {
+                case POST_PLAIN:
+                case POST_MATVEC: a.out0[i] = t0; break;
+                case POST_RESID: {
+                    const double rp = t0 - a.b[i];
+                    a.out0[i] = rp;
+                    a.out1[i] = a.b[i] - t1;
+                    contrib = rp * rp;
+                    break;
+                }
+                case POST_RHAT: a.out0[i] = t0 - a.pvec[i]; break;
+                default: break;
+            }
+        }
+    }
+    if (a.post == POST_RESID) {
+        const double tot = block_sum(contrib, shr);
+        if (threadIdx.x == 0) a.gpart[blockIdx.x] = tot;   // per-block sums of r_p^2
+        if (blockIdx.x == 0 && ncr > 0) {
+            double s = 0.0;
+            for (int g = threadIdx.x; g < G; g += RNT) s += a.colpart[g];
+            s = block_sum(s, shr);
+            if (threadIdx.x == 0) a.outsc[1] = s;   // sum of r_d^2
+        }
+    }
+}
+
+template <typename T, typename ACC, int NT, int RPT, int LPR, bool PF, class Op>
 __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
+    static_assert(LPR == 4 || LPR == 8 || LPR == 16 || LPR == 32 || LPR == 64, "LPR");
     constexpr int VEC = Elem<T>::VEC;
     constexpr int SW = LPR * VEC;
     constexpr int RG = NT / LPR;
     constexpr int NW = NT / 64;
-    constexpr int ND = Op::NDOT, NA = Op::NACC, NCR = Op::NCR;
+    constexpr int NA = Op::NACC, NCR = Op::NCR;
     constexpr int MPAD = RG * RPT;
 
     if (a.done != nullptr && *a.done) return;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    ACC* vs = reinterpret_cast<ACC*>(smem_raw);          // [MPAD]   vector dotted with columns
-    ACC* red = vs + ND * MPAD;                              // [2][NW][SW][ND]
+    ACC* vs = reinterpret_cast<ACC*>(smem_raw);   // [MPAD]        vector dotted with columns
+    ACC* red = vs + MPAD;                            // [2][NW][SW]   per-wave column dots
     __shared__ double shr[NW];
 
     const int tid = threadIdx.x;
     const int c = tid % LPR, g = tid / LPR, lane = tid & 63, wid = tid >> 6;
     const int m = a.m;
+    const int G = gridDim.x;
     const T* __restrict__ A = reinterpret_cast<const T*>(a.A);
 
     for (int i = tid; i < MPAD; i += NT) vs[i] = (i < m) ? (ACC)a.vec0[i] : (ACC)0;
     __syncthreads();
     const typename Op::S st = Op::init(a);
+
+    auto load = [&](int strip, ACC (&dst)[RPT][VEC]) {
+        const int64_t j0 = (int64_t)strip * SW + c * VEC;
+        const bool full = (j0 + VEC <= a.n);
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = g + RG * k;
+            if (i < m) {
+                const T* ptr = A + (int64_t)i * a.ld + j0;
+                if (full) {
+                    Elem<T>::template load16<ACC>(ptr, dst[k]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        dst[k][e] = (j0 + e < a.n) ? (ACC)Elem<T>::load1(ptr + e) : (ACC)0;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) dst[k][e] = (ACC)0;
+            }
+        }
+    };
 
     ACC q[NA][RPT];
 #pragma unroll
@@ -96,27 +171,18 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     double cr[NCR > 0 ? NCR : 1] = {0.0};
 
     int buf = 0;
-    for (int strip = blockIdx.x; strip < nstrips; strip += gridDim.x) {
-        const int64_t j0 = (int64_t)strip * SW + c * VEC;
-        const bool full = (j0 + VEC <= a.n);
-        ACC av[RPT][VEC];
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const int i = g + RG * k;
-            if (i < m) {
-                const T* ptr = A + (int64_t)i * a.ld + j0;
-                if (full) {
-                    Elem<T>::template load16<ACC>(ptr, av[k]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e)
-                        av[k][e] = (j0 + e < a.n) ? (ACC)Elem<T>::load1(ptr + e) : (ACC)0;
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) av[k][e] = (ACC)0;
-            }
+    ACC av[RPT][VEC];
+    int strip = blockIdx.x;
+    if (PF && strip < nstrips) load(strip, av);
+    for (; strip < nstrips; strip += G) {
+        ACC nx[RPT][VEC];
+        const bool has_next = PF && (strip + G < nstrips);
+        if constexpr (PF) {
+            if (has_next) load(strip + G, nx);
+        } else {
+            load(strip, av);
         }
+        const int64_t j0 = (int64_t)strip * SW + c * VEC;
         // column dots over this thread's rows
         ACC pd[VEC];
 #pragma unroll
@@ -127,13 +193,12 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) pd[e] += av[k][e] * vv;
         }
-        // over the 8 row groups of this wave (lane bits 3..5)
+        // over the 64/LPR row groups of this wave (lane bits log2(LPR)..5)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             ACC v = pd[e];
-            v += __shfl_xor(v, 8, 64);
-            v += __shfl_xor(v, 16, 64);
-            v += __shfl_xor(v, 32, 64);
+#pragma unroll
+            for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
             pd[e] = v;
         }
         ACC* rb = red + buf * NW * SW;
@@ -150,7 +215,7 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
             for (int w = 0; w < NW; ++w) t += rb[w * SW + c * VEC + e];
             ACC cf[NA];
             const int64_t j = j0 + e;
-            Op::template column<ACC>(a, st, j, j < a.n, g == 0, &t, cf, cr);
+            Op::template column<ACC>(a, st, j, j < a.n, g == 0, t, cf, cr);
 #pragma unroll
             for (int aa = 0; aa < NA; ++aa) coef[aa][e] = cf[aa];
         }
@@ -164,17 +229,24 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
                 q[aa][k] += sacc;
             }
         buf ^= 1;
+        if constexpr (PF) {
+            if (has_next) {
+#pragma unroll
+                for (int k = 0; k < RPT; ++k)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) av[k][e] = nx[k][e];
+            }
+        }
     }
 
-    // row sums over the 8 column lanes of each row group
+    // row sums over the LPR column lanes of each row group
 #pragma unroll
     for (int aa = 0; aa < NA; ++aa)
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
             ACC v = q[aa][k];
-            v += __shfl_xor(v, 1, 64);
-            v += __shfl_xor(v, 2, 64);
-            v += __shfl_xor(v, 4, 64);
+#pragma unroll
+            for (int o = 1; o < LPR; o <<= 1) v += __shfl_xor(v, o, 64);
             q[aa][k] = v;
         }
     if (c == 0) {
@@ -183,7 +255,7 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
 #pragma unroll
             for (int k = 0; k < RPT; ++k) {
                 const int i = g + RG * k;
-                if (i < m) a.part[((int64_t)aa * gridDim.x + blockIdx.x) * m + i] = (double)q[aa][k];
+                if (i < m) a.part[((int64_t)aa * m + i) * G + blockIdx.x] = (double)q[aa][k];
             }
     }
     if constexpr (NCR > 0) {
@@ -198,10 +270,10 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
 template <typename T, typename ACC, int NT, class Op>
 hipError_t dispatch_rpt(const StripCall& c, const StripPlan& p, hipStream_t st) {
     switch (p.rpt) {
-#define IPM_RPT_CASE(R)                                                                          \
-    case R:                                                                                      \
-        hipLaunchKernelGGL((k_strip<T, ACC, NT, R, Op>), dim3(p.grid), dim3(NT), p.lds, st, c,  \
-                           p.nstrips);                                                           \
+#define IPM_RPT_CASE(R)                                                                                   \
+    case R:                                                                                               \
+        hipLaunchKernelGGL((k_strip<T, ACC, NT, R, kLpr, false, Op>), dim3(p.grid), dim3(NT), p.lds, st, c, \
+                           p.nstrips);                                                                    \
         break;
         IPM_RPT_CASE(1)
         IPM_RPT_CASE(2)
@@ -232,86 +304,42 @@ hipError_t dispatch_type(const StripCall& c, const StripPlan& p, hipStream_t st)
     }
 }
 
-// ---- row reduction of the partials ------------------------------------------------------------
-constexpr int RR_ROWS = 16, RR_SLICES = 16;
-
-template <int POST>
-__global__ __launch_bounds__(256) void k_reduce_rows(const double* __restrict__ part, int G, int m, int nacc,
-                                                     const double* __restrict__ b, const double* __restrict__ pvec,
-                                                     const double* __restrict__ dvec, double* __restrict__ out0,
-                                                     double* __restrict__ out1, double* __restrict__ blockpart,
-                                                     const int* __restrict__ done) {
-    if (done != nullptr && *done) return;
-    __shared__ double sh[2][RR_SLICES][RR_ROWS + 1];
-    __shared__ double shr[4];
-    const int tr = threadIdx.x % RR_ROWS, sl = threadIdx.x / RR_ROWS;
-    const int i = blockIdx.x * RR_ROWS + tr;
-    double s0 = 0.0, s1 = 0.0;
-    if (i < m) {
-        for (int g = sl; g < G; g += RR_SLICES) {
-            s0 += part[(int64_t)g * m + i];
-            if (nacc > 1) s1 += part[((int64_t)G + g) * m + i];
-        }
-    }
-    sh[0][sl][tr] = s0;
-    sh[1][sl][tr] = s1;
-    __syncthreads();
-    double contrib = 0.0;
-    if (sl == 0 && i < m) {
-        double t0 = 0.0, t1 = 0.0;
-        for (int k = 0; k < RR_SLICES; ++k) { t0 += sh[0][k][tr]; t1 += sh[1][k][tr]; }
-        if (POST == POST_PLAIN) {
-            out0[i] = t0;
-        } else if (POST == POST_MATVEC) {
-            out0[i] = t0;
-            contrib = dvec[i] * t0;
-        } else if (POST == POST_RESID) {
-            const double rp = t0 - b[i];
-            out0[i] = rp;
-            out1[i] = b[i] - t1;
-            contrib = rp * rp;
-        } else if (POST == POST_RHAT) {
-            out0[i] = t0 - pvec[i];
-        }
-    }
-    if (POST == POST_MATVEC || POST == POST_RESID) {
-        const double t = block_sum(contrib, shr);
-        if (threadIdx.x == 0) blockpart[blockIdx.x] = t;
-    }
-}
-
 }  // namespace
 
+int rowsum_blocks(int m) { return (m + RNT / 64 - 1) / (RNT / 64); }
+
 StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind) {
+    (void)kind;
     StripPlan p{};
     const int vec = dtype == 0 ? 2 : (dtype == 1 ? 4 : 8);
-    p.sw = LPR * vec;
+    p.sw = kLpr * vec;
     p.nstrips = (int)((n + p.sw - 1) / p.sw);
     // rows per thread: smallest instance covering m with 256 threads, else 1024 threads
     static const int rpts[] = {1, 2, 4, 8, 12, 16};
     p.nt = 0;
     for (int nt : {256, 1024}) {
-        const int rg = nt / LPR;
+        const int rg = nt / kLpr;
         for (int r : rpts)
             if (r * rg >= m) { p.nt = nt; p.rpt = r; break; }
         if (p.nt) break;
     }
     if (!p.nt) { p.nt = -1; return p; }   // m too large for the dense strip pass
-    const int per_cu = p.nt == 256 ? 4 : 1;
+    // two blocks of 256 threads per CU measured best on MI355X for the 500-row FP64 pass
+    const int per_cu = p.nt == 256 ? 2 : 1;
     int grid = num_cu * per_cu;
     if (grid > p.nstrips) grid = p.nstrips;
+    if (grid > kStripMaxGrid) grid = kStripMaxGrid;
     if (grid < 1) grid = 1;
     p.grid = grid;
-    const int rg = p.nt / LPR;
+    const int rg = p.nt / kLpr;
     const int nw = p.nt / 64;
     const size_t acc = 8;   // sized for FP64 accumulation (enough for FP32 too)
-    (void)kind;
     p.lds = acc * ((size_t)rg * p.rpt + 2 * (size_t)nw * p.sw);
     return p;
 }
 
-hipError_t launch_strip(const StripCall& c, const StripPlan& p, hipStream_t st) {
-    if (p.nt <= 0) return hipErrorInvalidValue;
+hipError_t launch_strip_pass(const StripCall& c, const StripPlan& p, hipStream_t st) {
+    if (p.nt <= 0 || p.grid > kStripMaxGrid) return hipErrorInvalidValue;
     switch (c.kind) {
         case STRIP_MATVEC: return dispatch_type<OpMatvec>(c, p, st);
         case STRIP_RESID: return dispatch_type<OpResid>(c, p, st);
@@ -320,32 +348,17 @@ hipError_t launch_strip(const StripCall& c, const StripPlan& p, hipStream_t st) 
     }
 }
 
-int reduce_rows_blocks(int m) { return (m + RR_ROWS - 1) / RR_ROWS; }
-
-hipError_t launch_reduce_rows(int post, const double* part, int G, int m, int nacc, const double* b,
-                              const double* pvec, const double* dvec, double* out0, double* out1,
-                              double* blockpart, const int* done, hipStream_t st) {
-    const dim3 grid(reduce_rows_blocks(m)), block(256);
-    switch (post) {
-        case POST_PLAIN:
-            hipLaunchKernelGGL(k_reduce_rows<POST_PLAIN>, grid, block, 0, st, part, G, m, nacc, b, pvec, dvec, out0,
-                               out1, blockpart, done);
-            break;
-        case POST_MATVEC:
-            hipLaunchKernelGGL(k_reduce_rows<POST_MATVEC>, grid, block, 0, st, part, G, m, nacc, b, pvec, dvec,
-                               out0, out1, blockpart, done);
-            break;
-        case POST_RESID:
-            hipLaunchKernelGGL(k_reduce_rows<POST_RESID>, grid, block, 0, st, part, G, m, nacc, b, pvec, dvec,
-                               out0, out1, blockpart, done);
-            break;
-        case POST_RHAT:
-            hipLaunchKernelGGL(k_reduce_rows<POST_RHAT>, grid, block, 0, st, part, G, m, nacc, b, pvec, dvec, out0,
-                               out1, blockpart, done);
-            break;
-        default: return hipErrorInvalidValue;
-    }
+hipError_t launch_strip_rowsum(const StripCall& c, const StripPlan& p, hipStream_t st) {
+    const int nacc = c.kind == STRIP_RESID ? 2 : 1;
+    const int ncr = c.kind == STRIP_RESID ? 1 : 0;
+    hipLaunchKernelGGL(k_rowsum, dim3(rowsum_blocks(c.m)), dim3(RNT), 0, st, c, p.grid, nacc, ncr);
     return hipGetLastError();
+}
+
+hipError_t launch_strip(const StripCall& c, const StripPlan& p, hipStream_t st) {
+    hipError_t e = launch_strip_pass(c, p, st);
+    if (e != hipSuccess) return e;
+    return launch_strip_rowsum(c, p, st);
 }
 
 }  // namespace ipmsk
