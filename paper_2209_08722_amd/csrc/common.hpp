@@ -1,10 +1,30 @@
 // Shared device helpers for the ipmsk HIP kernels (gfx950, wave64).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace ipmsk {
+
+// Events for the next measured launch. When set, IPM_LAUNCH launches through
+// hipExtLaunchKernelGGL, which records them at the kernel's own start and end, and clears them.
+struct LaunchTiming {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+extern thread_local LaunchTiming g_launch_timing;
+
+#define IPM_LAUNCH(kernel, grid, block, shmem, stream, ...)                                            \
+    do {                                                                                              \
+        if (::ipmsk::g_launch_timing.start != nullptr) {                                              \
+            hipEvent_t ev0_ = ::ipmsk::g_launch_timing.start, ev1_ = ::ipmsk::g_launch_timing.stop;    \
+            ::ipmsk::g_launch_timing = ::ipmsk::LaunchTiming{};                                       \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev0_, ev1_, 0, __VA_ARGS__);     \
+        } else {                                                                                      \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                       \
+        }                                                                                             \
+    } while (0)
 
 constexpr uint64_t kPhi = 0x9E3779B97F4A7C15ull;
 
@@ -90,40 +110,50 @@ __device__ __forceinline__ float bf16_to_float(uint32_t bits16) { return __uint_
 
 template <typename T> struct Elem;
 
-// 16-byte vector loads converted to the accumulation type ACC (float or double).
+// 16-byte raw loads (kept as 4 dwords in registers) and conversion of element e to the
+// accumulation type ACC (float or double) at the point of use.
 template <> struct Elem<double> {
     static constexpr int VEC = 2;   // elements per 16-byte load
+    __device__ __forceinline__ static uint4 raw16(const double* p) { return *reinterpret_cast<const uint4*>(p); }
     template <typename ACC>
-    __device__ __forceinline__ static void load16(const double* p, ACC* o) {
-        const double2 v = *reinterpret_cast<const double2*>(p);
-        o[0] = (ACC)v.x; o[1] = (ACC)v.y;
+    __device__ __forceinline__ static ACC get(const uint4& v, int e) {
+        const uint32_t lo = e == 0 ? v.x : v.z, hi = e == 0 ? v.y : v.w;
+        return (ACC)__hiloint2double((int)hi, (int)lo);
     }
     __device__ __forceinline__ static double load1(const double* p) { return *p; }
 };
 
 template <> struct Elem<float> {
     static constexpr int VEC = 4;
+    __device__ __forceinline__ static uint4 raw16(const float* p) { return *reinterpret_cast<const uint4*>(p); }
     template <typename ACC>
-    __device__ __forceinline__ static void load16(const float* p, ACC* o) {
-        const float4 v = *reinterpret_cast<const float4*>(p);
-        o[0] = (ACC)v.x; o[1] = (ACC)v.y; o[2] = (ACC)v.z; o[3] = (ACC)v.w;
+    __device__ __forceinline__ static ACC get(const uint4& v, int e) {
+        const uint32_t w = e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+        return (ACC)__uint_as_float(w);
     }
     __device__ __forceinline__ static float load1(const float* p) { return *p; }
 };
 
 template <> struct Elem<bf16_t> {
     static constexpr int VEC = 8;
+    __device__ __forceinline__ static uint4 raw16(const bf16_t* p) { return *reinterpret_cast<const uint4*>(p); }
     template <typename ACC>
-    __device__ __forceinline__ static void load16(const bf16_t* p, ACC* o) {
-        const uint4 v = *reinterpret_cast<const uint4*>(p);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            o[2 * q] = (ACC)__uint_as_float(w[q] << 16);
-            o[2 * q + 1] = (ACC)__uint_as_float(w[q] & 0xFFFF0000u);
-        }
+    __device__ __forceinline__ static ACC get(const uint4& v, int e) {
+        const uint32_t w = (e >> 1) == 0 ? v.x : ((e >> 1) == 1 ? v.y : ((e >> 1) == 2 ? v.z : v.w));
+        return (ACC)__uint_as_float((e & 1) ? (w & 0xFFFF0000u) : (w << 16));
     }
     __device__ __forceinline__ static float load1(const bf16_t* p) { return bf16_to_float(*p); }
 };
+
+// Raw 16-byte word holding elements [0, cnt) read one by one (tail of a row), zero elsewhere.
+template <typename T>
+__device__ __forceinline__ uint4 raw_partial(const T* p, int cnt) {
+    union { uint4 v; T e[16 / sizeof(T)]; } u;
+    u.v = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int e = 0; e < (int)(16 / sizeof(T)); ++e)
+        if (e < cnt) u.e[e] = p[e];
+    return u.v;
+}
 
 }  // namespace ipmsk

@@ -96,17 +96,26 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
             }
 }
 
+// Broadcast lane `lane` of a double held in a VGPR (lane is a compile-time constant here).
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
 // Factor the kb x kb diagonal block at (k0, k0) of the partially updated matrix in place
 // (lower triangle) and write its inverse into X's diagonal block (zero above the diagonal).
-// One wave. Lane t keeps row t of the block in registers during the factorization (right-looking:
-// the scaled column c is shared through LDS) and column t of the inverse during the forward
-// substitution X L = I (rows of L broadcast from LDS). Loops are fully unrolled so the row and
-// column arrays stay in registers. A pivot that is not positive is recorded in *status (smallest
-// index wins) and replaced by 1 so the remaining work stays finite.
+// One wave. Lane t keeps row t of the block in registers. Step c of the right-looking
+// factorization scales column c, publishes it in LDS and every lane updates its row with
+// broadcast reads of that column; the update is applied to all j > c (for j > t it only touches
+// the unused upper part of the row), which keeps the unrolled code free of predication. The
+// inverse's column t comes from forward substitution X L = I with the rows of L broadcast from
+// LDS and four independent accumulators. A pivot that is not positive is recorded in *status
+// (smallest index wins) and replaced by 1 so the remaining work stays finite.
 __global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ Lw, int64_t ld, int k0, int kb,
                                                    double* __restrict__ X, int64_t ldx, int* __restrict__ status) {
-    __shared__ double col[64];
-    __shared__ double Ls[64][65];
+    __shared__ __align__(16) double col[64];
+    __shared__ __align__(16) double Ls[64][64];
     const int t = threadIdx.x;
     double r[64];
     const double* src = Lw + (int64_t)(k0 + (t < kb ? t : 0)) * ld + k0;
@@ -115,7 +124,7 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ Lw, int6
 #pragma unroll
     for (int c = 0; c < 64; ++c) {
         if (c < kb) {
-            double piv = __shfl(r[c], c, 64);
+            double piv = readlane_d(r[c], c);
             if (!(piv > 0.0)) {
                 if (t == 0) atomicMin(status, k0 + c);
                 piv = 1.0;
@@ -128,32 +137,35 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ Lw, int6
             __syncthreads();
             const double ltc = r[c];
 #pragma unroll
-            for (int j = c + 1; j < 64; ++j) {
-                const double ljc = col[j];
-                if (t > c && j <= t) r[j] -= ltc * ljc;
-            }
+            for (int j = c + 1; j < 64; ++j) r[j] = fma(-ltc, col[j], r[j]);
             __syncthreads();
         }
     }
-    // row t of L to LDS (for the inverse) and back to global memory
-#pragma unroll
-    for (int j = 0; j < 64; ++j) Ls[t][j] = r[j];
     if (t < kb) {
         double* dst = Lw + (int64_t)(k0 + t) * ld + k0;
 #pragma unroll
         for (int j = 0; j < 64; ++j)
             if (j <= t) dst[j] = r[j];
     }
+#pragma unroll
+    for (int j = 0; j < 64; ++j) Ls[t][j] = (j <= t) ? r[j] : 0.0;
     __syncthreads();
     // column t of X = L^{-1}: X[i][t] = (delta_it - sum_{q<i} L[i][q] X[q][t]) / L[i][i]
     double x[64];
 #pragma unroll
     for (int i = 0; i < 64; ++i) {
         if (i < kb) {
-            double s = (i == t) ? 1.0 : 0.0;
+            double s0 = (i == t) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-            for (int q = 0; q < i; ++q) s -= Ls[i][q] * x[q];
-            x[i] = s / Ls[i][i];
+            for (int q = 0; q + 3 < i; q += 4) {
+                s0 = fma(-Ls[i][q], x[q], s0);
+                s1 = fma(-Ls[i][q + 1], x[q + 1], s1);
+                s2 = fma(-Ls[i][q + 2], x[q + 2], s2);
+                s3 = fma(-Ls[i][q + 3], x[q + 3], s3);
+            }
+#pragma unroll
+            for (int q = i & ~3; q < i; ++q) s0 = fma(-Ls[i][q], x[q], s0);
+            x[i] = ((s0 + s1) + (s2 + s3)) / Ls[i][i];
         } else {
             x[i] = 0.0;
         }
@@ -200,8 +212,8 @@ hipError_t gemm_go(int M, int N, int K, double alpha, const TIN* A, int64_t lda,
     if (kchunk < GK) kchunk = GK;
     ksplit = K > 0 ? (K + kchunk - 1) / kchunk : 1;
     const dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, ksplit);
-    hipLaunchKernelGGL((k_gemm<TB, LO, TIN>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                       kchunk, ksplit > 1 ? 1 : 0);
+    IPM_LAUNCH((k_gemm<TB, LO, TIN>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+               ksplit > 1 ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -13,6 +13,10 @@
 
 using namespace ipmsk;
 
+namespace ipmsk {
+thread_local LaunchTiming g_launch_timing;
+}
+
 namespace {
 
 enum WsId {
@@ -111,7 +115,8 @@ hipEvent_t pool_event(ipm_ctx* ctx) {
     return e;
 }
 
-// Begin/end a timed region around one launch of a measured kernel.
+// Timing of the next launch of a measured kernel: the events are handed to the launch
+// (hipExtLaunchKernelGGL records them at the kernel's own start and end).
 struct Timer {
     ipm_ctx* ctx;
     int kernel;
@@ -121,12 +126,12 @@ struct Timer {
         if (ctx->timing) {
             a = pool_event(ctx);
             b = pool_event(ctx);
-            if (a) (void)hipEventRecord(a, ctx->stream);
+            if (a && b) g_launch_timing = LaunchTiming{a, b};
         }
     }
     void stop() {
+        g_launch_timing = LaunchTiming{};
         if (ctx->timing && a && b) {
-            (void)hipEventRecord(b, ctx->stream);
             ctx->pending[kernel].push_back(TimedPair{a, b, tag});
             a = b = nullptr;
         }

@@ -38,6 +38,54 @@ __device__ __forceinline__ double row_dot_upper(const double* __restrict__ M, in
     return wave_sum(acc);
 }
 
+// The first 512 entries of a wave's row are loaded into registers before the block-wide
+// reductions and the staging of the vector, so their latency overlaps that work.
+constexpr int PRE = 8;
+
+__device__ __forceinline__ void preload_lower(const double* __restrict__ M, int m, int row, int lane, double* mv) {
+    const double* mr = M + (int64_t)row * m;
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+        const int l = lane + 64 * u;
+        mv[u] = (row < m && l <= row) ? mr[l] : 0.0;
+    }
+}
+
+__device__ __forceinline__ double finish_lower(const double* __restrict__ M, int m, int row, const double* xs,
+                                               int lane, const double* mv) {
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+        const int l = lane + 64 * u;
+        if (l <= row) acc += mv[u] * xs[l];
+    }
+    const double* mr = M + (int64_t)row * m;
+    for (int l = lane + 64 * PRE; l <= row; l += 64) acc += mr[l] * xs[l];
+    return wave_sum(acc);
+}
+
+__device__ __forceinline__ void preload_upper(const double* __restrict__ M, int m, int row, int lane, double* mv) {
+    const double* mr = M + (int64_t)row * m;
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+        const int l = row + lane + 64 * u;
+        mv[u] = (row < m && l < m) ? mr[l] : 0.0;
+    }
+}
+
+__device__ __forceinline__ double finish_upper(const double* __restrict__ M, int m, int row, const double* xs,
+                                               int lane, const double* mv) {
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+        const int l = row + lane + 64 * u;
+        if (l < m) acc += mv[u] * xs[l];
+    }
+    const double* mr = M + (int64_t)row * m;
+    for (int l = row + lane + 64 * PRE; l < m; l += 64) acc += mr[l] * xs[l];
+    return wave_sum(acc);
+}
+
 __global__ __launch_bounds__(GNT) void k_pcg_init1(PcgBufs b, int warm) {
     extern __shared__ double xs[];   // [2][m]
     __shared__ double sh[GNW];
@@ -98,6 +146,9 @@ __global__ __launch_bounds__(GNT) void k_pcg_gemv1(PcgBufs b, int j) {
     __shared__ double sh[GNW];
     const int m = b.m, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int par = j & 1;
+    const int row0 = blockIdx.x * GNW + wid;
+    double mv[PRE];
+    preload_lower(b.X, m, row0, lane, mv);
     double dqp = 0.0;
     for (int l = tid; l < m; l += GNT) dqp += b.dv[l] * b.q[l];
     const double dq = block_sum(dqp, sh);
@@ -121,12 +172,13 @@ __global__ __launch_bounds__(GNT) void k_pcg_gemv1(PcgBufs b, int j) {
     }
     __syncthreads();
     double s = 0.0;
-    for (int row = blockIdx.x * GNW + wid; row < m; row += gridDim.x * GNW) {
-        const double w = row_dot_lower(b.X, m, row, xs, lane);
+    for (int row = row0; row < m; row += gridDim.x * GNW) {
+        if (row != row0) preload_lower(b.X, m, row, lane, mv);
+        const double w = finish_lower(b.X, m, row, xs, lane, mv);
         if (lane == 0) { b.wv[row] = w; s += w * w; }
     }
-    const double t = block_sum(s, sh);
-    if (tid == 0) b.rho_part[blockIdx.x] = t;
+    const double tt = block_sum(s, sh);
+    if (tid == 0) b.rho_part[blockIdx.x] = tt;
 }
 
 __global__ __launch_bounds__(GNT) void k_pcg_gemv2(PcgBufs b, int j) {
@@ -135,12 +187,16 @@ __global__ __launch_bounds__(GNT) void k_pcg_gemv2(PcgBufs b, int j) {
     __shared__ double sh[GNW];
     const int m = b.m, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int par = j & 1;
+    const int row0 = blockIdx.x * GNW + wid;
+    double mv[PRE];
+    preload_upper(b.XT, m, row0, lane, mv);
     const double rho_new = sum_partials(b.rho_part, b.n_rho, 1, sh);
     const double beta = rho_new / b.cd[PD_RHO0 + par];
     for (int l = tid; l < m; l += GNT) xs[l] = b.wv[l];
     __syncthreads();
-    for (int row = blockIdx.x * GNW + wid; row < m; row += gridDim.x * GNW) {
-        const double z = row_dot_upper(b.XT, m, row, xs, lane);
+    for (int row = row0; row < m; row += gridDim.x * GNW) {
+        if (row != row0) preload_upper(b.XT, m, row, lane, mv);
+        const double z = finish_upper(b.XT, m, row, xs, lane, mv);
         if (lane == 0) b.dv[row] = z + beta * b.dv[row];
     }
     if (blockIdx.x == 0 && tid == 0) {

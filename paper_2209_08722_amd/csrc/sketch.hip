@@ -94,8 +94,8 @@ template <typename T, typename BT, int R>
 void sketch_go(const T* A, int m, int64_t n, int64_t ld, const double* dv, int d2, const HashKeys& hk, int w,
                BT* B, const SketchPlan& sp, hipStream_t st) {
     const dim3 grid((m + R - 1) / R, sp.chunks);
-    hipLaunchKernelGGL((k_sketch_lds<T, BT, R>), grid, dim3(SNT), sp.lds, st, A, m, n, ld, dv, d2, hk, w,
-                       sp.cols_per_chunk, B, sp.atomic ? 1 : 0);
+    IPM_LAUNCH((k_sketch_lds<T, BT, R>), grid, dim3(SNT), sp.lds, st, A, m, n, ld, dv, d2, hk, w,
+               sp.cols_per_chunk, B, sp.atomic ? 1 : 0);
 }
 
 template <typename T, typename BT>
@@ -106,7 +106,7 @@ hipError_t sketch_type(const void* Av, int m, int64_t n, int64_t ld, const doubl
     if (sp.global_only) {
         int gx = (int)((n + SNT - 1) / SNT);
         if (gx > 64) gx = 64;
-        hipLaunchKernelGGL((k_sketch_global<T, BT>), dim3(gx, m), dim3(SNT), 0, st, A, m, n, ld, dv, d2, hk, w, B);
+        IPM_LAUNCH((k_sketch_global<T, BT>), dim3(gx, m), dim3(SNT), 0, st, A, m, n, ld, dv, d2, hk, w, B);
         return hipGetLastError();
     }
     switch (sp.rows_per_block) {

@@ -9,9 +9,10 @@
 //     [strip*SW + c*VEC, +VEC);
 //   - column dots: per-thread partials, then wave shuffles over the row groups of a wave, then
 //     one LDS exchange across waves (double-buffered, one barrier per strip);
-//   - row sums: per-thread register accumulators, reduced over the column lanes once at the end
-//     of the persistent loop;
-//   - optionally the next strip's loads are issued before the current strip is reduced;
+//   - the strip stays in registers as raw 16-byte words, converted to the accumulation type at use;
+//   - row sums: per-thread register accumulators reduced over the column lanes once at the end
+//     of the persistent loop, or (more than 16 rows per thread) reduced over the column lanes
+//     every strip and added into an LDS row-sum array;
 //   - each block writes its partial row sums as part[acc][row][block]; a second kernel reduces
 //     them with one wave per row (coalesced over blocks) in a fixed order and applies the
 //     post-processing step (r_p, p, the true residual, ...).
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(RNT) void k_rowsum(StripCall a, int G, int nacc, in
     }
 }
 
-template <typename T, typename ACC, int NT, int RPT, int LPR, bool PF, class Op>
+template <typename T, typename ACC, int NT, int RPT, int LPR, bool QL, class Op>
 __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     static_assert(LPR == 4 || LPR == 8 || LPR == 16 || LPR == 32 || LPR == 64, "LPR");
     constexpr int VEC = Elem<T>::VEC;
@@ -129,6 +130,7 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     ACC* vs = reinterpret_cast<ACC*>(smem_raw);   // [MPAD]        vector dotted with columns
     ACC* red = vs + MPAD;                            // [2][NW][SW]   per-wave column dots
+    double* qs = reinterpret_cast<double*>(red + 2 * NW * SW);   // [NA][MPAD] row sums (QL only)
     __shared__ double shr[NW];
 
     const int tid = threadIdx.x;
@@ -138,51 +140,37 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     const T* __restrict__ A = reinterpret_cast<const T*>(a.A);
 
     for (int i = tid; i < MPAD; i += NT) vs[i] = (i < m) ? (ACC)a.vec0[i] : (ACC)0;
+    if constexpr (QL) {
+        for (int i = tid; i < NA * MPAD; i += NT) qs[i] = 0.0;
+    }
     __syncthreads();
     const typename Op::S st = Op::init(a);
 
-    auto load = [&](int strip, ACC (&dst)[RPT][VEC]) {
-        const int64_t j0 = (int64_t)strip * SW + c * VEC;
-        const bool full = (j0 + VEC <= a.n);
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const int i = g + RG * k;
-            if (i < m) {
-                const T* ptr = A + (int64_t)i * a.ld + j0;
-                if (full) {
-                    Elem<T>::template load16<ACC>(ptr, dst[k]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e)
-                        dst[k][e] = (j0 + e < a.n) ? (ACC)Elem<T>::load1(ptr + e) : (ACC)0;
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) dst[k][e] = (ACC)0;
-            }
-        }
-    };
+    // Address of (row g + RG*k, column strip*SW + c*VEC): a uniform part (strip, k) plus a
+    // per-thread offset that stays the same for every strip and row block, so the loads use a
+    // scalar base and one 32-bit VGPR offset.
+    const uint32_t lane_off = (uint32_t)g * (uint32_t)a.ld + (uint32_t)(c * VEC);
 
-    ACC q[NA][RPT];
+    ACC q[NA][QL ? 1 : RPT];
 #pragma unroll
     for (int aa = 0; aa < NA; ++aa)
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) q[aa][k] = (ACC)0;
+        for (int k = 0; k < (QL ? 1 : RPT); ++k) q[aa][k] = (ACC)0;
     double cr[NCR > 0 ? NCR : 1] = {0.0};
 
     int buf = 0;
-    ACC av[RPT][VEC];
-    int strip = blockIdx.x;
-    if (PF && strip < nstrips) load(strip, av);
-    for (; strip < nstrips; strip += G) {
-        ACC nx[RPT][VEC];
-        const bool has_next = PF && (strip + G < nstrips);
-        if constexpr (PF) {
-            if (has_next) load(strip + G, nx);
-        } else {
-            load(strip, av);
-        }
+    for (int strip = blockIdx.x; strip < nstrips; strip += G) {
         const int64_t j0 = (int64_t)strip * SW + c * VEC;
+        const int64_t left = a.n - j0;
+        uint4 av[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int i = g + RG * k;
+            const T* ptr = A + (int64_t)strip * SW + (int64_t)(RG * k) * a.ld + lane_off;
+            if (i < m && left >= VEC) av[k] = Elem<T>::raw16(ptr);
+            else if (i < m && left > 0) av[k] = raw_partial<T>(ptr, (int)left);
+            else av[k] = make_uint4(0u, 0u, 0u, 0u);
+        }
         // column dots over this thread's rows
         ACC pd[VEC];
 #pragma unroll
@@ -191,7 +179,7 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
         for (int k = 0; k < RPT; ++k) {
             const ACC vv = vs[g + RG * k];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) pd[e] += av[k][e] * vv;
+            for (int e = 0; e < VEC; ++e) pd[e] += Elem<T>::template get<ACC>(av[k], e) * vv;
         }
         // over the 64/LPR row groups of this wave (lane bits log2(LPR)..5)
 #pragma unroll
@@ -219,44 +207,55 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
 #pragma unroll
             for (int aa = 0; aa < NA; ++aa) coef[aa][e] = cf[aa];
         }
+        // Keep the strip as raw words across the barrier: without this the compiler holds the
+        // already converted elements of the dot phase live (up to 4x the registers) instead of
+        // converting again. The empty asm emits no instruction.
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) asm volatile("" : "+v"(av[k].x), "+v"(av[k].y), "+v"(av[k].z), "+v"(av[k].w));
 #pragma unroll
         for (int k = 0; k < RPT; ++k)
 #pragma unroll
             for (int aa = 0; aa < NA; ++aa) {
                 ACC sacc = (ACC)0;
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) sacc += av[k][e] * coef[aa][e];
-                q[aa][k] += sacc;
+                for (int e = 0; e < VEC; ++e) sacc += Elem<T>::template get<ACC>(av[k], e) * coef[aa][e];
+                if constexpr (QL) {
+                    // sum over the LPR column lanes of this row, then one lane updates the LDS row sum
+#pragma unroll
+                    for (int o = 1; o < LPR; o <<= 1) sacc += __shfl_xor(sacc, o, 64);
+                    if (c == 0) qs[aa * MPAD + g + RG * k] += (double)sacc;
+                } else {
+                    q[aa][k] += sacc;
+                }
             }
         buf ^= 1;
-        if constexpr (PF) {
-            if (has_next) {
-#pragma unroll
-                for (int k = 0; k < RPT; ++k)
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) av[k][e] = nx[k][e];
-            }
-        }
     }
 
-    // row sums over the LPR column lanes of each row group
+    if constexpr (QL) {
+        __syncthreads();
+        for (int i = tid; i < m; i += NT)
 #pragma unroll
-    for (int aa = 0; aa < NA; ++aa)
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            ACC v = q[aa][k];
-#pragma unroll
-            for (int o = 1; o < LPR; o <<= 1) v += __shfl_xor(v, o, 64);
-            q[aa][k] = v;
-        }
-    if (c == 0) {
+            for (int aa = 0; aa < NA; ++aa) a.part[((int64_t)aa * m + i) * G + blockIdx.x] = qs[aa * MPAD + i];
+    } else {
+        // row sums over the LPR column lanes of each row group
 #pragma unroll
         for (int aa = 0; aa < NA; ++aa)
 #pragma unroll
             for (int k = 0; k < RPT; ++k) {
-                const int i = g + RG * k;
-                if (i < m) a.part[((int64_t)aa * m + i) * G + blockIdx.x] = (double)q[aa][k];
+                ACC v = q[aa][k];
+#pragma unroll
+                for (int o = 1; o < LPR; o <<= 1) v += __shfl_xor(v, o, 64);
+                q[aa][k] = v;
             }
+        if (c == 0) {
+#pragma unroll
+            for (int aa = 0; aa < NA; ++aa)
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    const int i = g + RG * k;
+                    if (i < m) a.part[((int64_t)aa * m + i) * G + blockIdx.x] = (double)q[aa][k];
+                }
+        }
     }
     if constexpr (NCR > 0) {
 #pragma unroll
@@ -267,32 +266,38 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     }
 }
 
-template <typename T, typename ACC, int NT, class Op>
-hipError_t dispatch_rpt(const StripCall& c, const StripPlan& p, hipStream_t st) {
-    switch (p.rpt) {
-#define IPM_RPT_CASE(R)                                                                                   \
-    case R:                                                                                               \
-        hipLaunchKernelGGL((k_strip<T, ACC, NT, R, kLpr, false, Op>), dim3(p.grid), dim3(NT), p.lds, st, c, \
-                           p.nstrips);                                                                    \
+#define IPM_RPT_CASE(NTV, R)                                                                               \
+    case R:                                                                                                \
+        IPM_LAUNCH((k_strip<T, ACC, NTV, R, kLpr, (R > 16), Op>), dim3(p.grid), dim3(NTV), p.lds, st, c,   \
+                   p.nstrips);                                                                             \
         break;
-        IPM_RPT_CASE(1)
-        IPM_RPT_CASE(2)
-        IPM_RPT_CASE(4)
-        IPM_RPT_CASE(8)
-        IPM_RPT_CASE(12)
-        IPM_RPT_CASE(16)
-#undef IPM_RPT_CASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
 
 template <typename T, typename ACC, class Op>
 hipError_t dispatch_nt(const StripCall& c, const StripPlan& p, hipStream_t st) {
-    if (p.nt == 256) return dispatch_rpt<T, ACC, 256, Op>(c, p, st);
-    if (p.nt == 1024) return dispatch_rpt<T, ACC, 1024, Op>(c, p, st);
-    return hipErrorInvalidValue;
+    if (p.nt == 256) {
+        switch (p.rpt) {
+            IPM_RPT_CASE(256, 1)
+            IPM_RPT_CASE(256, 2)
+            IPM_RPT_CASE(256, 4)
+            IPM_RPT_CASE(256, 8)
+            IPM_RPT_CASE(256, 12)
+            IPM_RPT_CASE(256, 16)
+            default: return hipErrorInvalidValue;
+        }
+    } else if (p.nt == 512) {
+        switch (p.rpt) {
+            IPM_RPT_CASE(512, 12)
+            IPM_RPT_CASE(512, 16)
+            IPM_RPT_CASE(512, 24)
+            IPM_RPT_CASE(512, 32)
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
+#undef IPM_RPT_CASE
 
 template <class Op>
 hipError_t dispatch_type(const StripCall& c, const StripPlan& p, hipStream_t st) {
@@ -314,17 +319,15 @@ StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind) {
     const int vec = dtype == 0 ? 2 : (dtype == 1 ? 4 : 8);
     p.sw = kLpr * vec;
     p.nstrips = (int)((n + p.sw - 1) / p.sw);
-    // rows per thread: smallest instance covering m with 256 threads, else 1024 threads
-    static const int rpts[] = {1, 2, 4, 8, 12, 16};
+    // rows per thread: the smallest instance covering m; 256-thread blocks (2 per CU, measured
+    // best for m <= 512), then 512-thread blocks with up to 32 rows per thread (one per CU)
+    struct Inst { int nt, rpt; };
+    static const Inst insts[] = {{256, 1}, {256, 2}, {256, 4}, {256, 8}, {256, 12}, {256, 16},
+                                 {512, 12}, {512, 16}, {512, 24}, {512, 32}};
     p.nt = 0;
-    for (int nt : {256, 1024}) {
-        const int rg = nt / kLpr;
-        for (int r : rpts)
-            if (r * rg >= m) { p.nt = nt; p.rpt = r; break; }
-        if (p.nt) break;
-    }
+    for (const Inst& in : insts)
+        if (in.rpt * (in.nt / kLpr) >= m) { p.nt = in.nt; p.rpt = in.rpt; break; }
     if (!p.nt) { p.nt = -1; return p; }   // m too large for the dense strip pass
-    // two blocks of 256 threads per CU measured best on MI355X for the 500-row FP64 pass
     const int per_cu = p.nt == 256 ? 2 : 1;
     int grid = num_cu * per_cu;
     if (grid > p.nstrips) grid = p.nstrips;
@@ -335,6 +338,7 @@ StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind) {
     const int nw = p.nt / 64;
     const size_t acc = 8;   // sized for FP64 accumulation (enough for FP32 too)
     p.lds = acc * ((size_t)rg * p.rpt + 2 * (size_t)nw * p.sw);
+    if (p.rpt > 16) p.lds += 8 * 2 * (size_t)rg * p.rpt;   // LDS row sums (up to 2 accumulators)
     return p;
 }
 

@@ -60,12 +60,16 @@ def test_normal_matvec_fp64(ctx, m, n):
     assert np.all(np.abs(q - ref) <= 64 * np.finfo(float).eps * (m + np.sqrt(n)) * bound + 1e-300)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_normal_matvec_low_storage(ctx, dtype):
-    m, n = 60, 3001
+@pytest.mark.parametrize("m,n,dtype", [(60, 3001, "f32"), (60, 3001, "bf16"), (1500, 4003, "f64"),
+                                       (2000, 3001, "f32"), (2000, 5003, "bf16")])
+def test_normal_matvec_low_storage(ctx, m, n, dtype):
     A = rand_lp_matrix(m, n, 5)
-    A = lpgen.bf16_round(A) if dtype == "bf16" else lpgen.f32_round(A)
-    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    if dtype == "bf16":
+        A, tdt = lpgen.bf16_round(A), torch.bfloat16
+    elif dtype == "f32":
+        A, tdt = lpgen.f32_round(A), torch.float32
+    else:
+        tdt = torch.float64
     rng = np.random.default_rng(2)
     d2 = np.exp(rng.uniform(-3, 3, n))
     v = rng.standard_normal(m)
