@@ -105,17 +105,15 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 
 // Factor the kb x kb diagonal block at (k0, k0) of the partially updated matrix in place
 // (lower triangle) and write its inverse into X's diagonal block (zero above the diagonal).
-// One wave. Lane t keeps row t of the block in registers. Step c of the right-looking
-// factorization scales column c, publishes it in LDS and every lane updates its row with
-// broadcast reads of that column; the update is applied to all j > c (for j > t it only touches
-// the unused upper part of the row), which keeps the unrolled code free of predication. The
-// inverse's column t comes from forward substitution X L = I with the rows of L broadcast from
-// LDS and four independent accumulators. A pivot that is not positive is recorded in *status
-// (smallest index wins) and replaced by 1 so the remaining work stays finite.
+// One wave, no LDS. Lane t keeps row t of the block in registers; step c of the right-looking
+// factorization reads l_jc from lane j's register with readlane (compile-time lane index) and
+// updates every j > c (for j > t that only touches the unused upper part of the row, which
+// keeps the unrolled code free of predication). The inverse's column t comes from forward
+// substitution X L = I, reading row i of L from lane i the same way, with four independent
+// accumulators. A pivot that is not positive is recorded in *status (smallest index wins) and
+// replaced by 1 so the remaining work stays finite.
 __global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ Lw, int64_t ld, int k0, int kb,
                                                    double* __restrict__ X, int64_t ldx, int* __restrict__ status) {
-    __shared__ __align__(16) double col[64];
-    __shared__ __align__(16) double Ls[64][64];
     const int t = threadIdx.x;
     double r[64];
     const double* src = Lw + (int64_t)(k0 + (t < kb ? t : 0)) * ld + k0;
@@ -131,14 +129,10 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ Lw, int6
             }
             const double lcc = sqrt(piv);
             const double inv = 1.0 / lcc;
-            if (t == c) r[c] = lcc;
-            else if (t > c) r[c] *= inv;
-            col[t] = r[c];
-            __syncthreads();
+            r[c] = (t == c) ? lcc : r[c] * inv;
             const double ltc = r[c];
 #pragma unroll
-            for (int j = c + 1; j < 64; ++j) r[j] = fma(-ltc, col[j], r[j]);
-            __syncthreads();
+            for (int j = c + 1; j < 64; ++j) r[j] = fma(-ltc, readlane_d(r[c], j), r[j]);
         }
     }
     if (t < kb) {
@@ -147,9 +141,6 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ Lw, int6
         for (int j = 0; j < 64; ++j)
             if (j <= t) dst[j] = r[j];
     }
-#pragma unroll
-    for (int j = 0; j < 64; ++j) Ls[t][j] = (j <= t) ? r[j] : 0.0;
-    __syncthreads();
     // column t of X = L^{-1}: X[i][t] = (delta_it - sum_{q<i} L[i][q] X[q][t]) / L[i][i]
     double x[64];
 #pragma unroll
@@ -158,14 +149,14 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ Lw, int6
             double s0 = (i == t) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
             for (int q = 0; q + 3 < i; q += 4) {
-                s0 = fma(-Ls[i][q], x[q], s0);
-                s1 = fma(-Ls[i][q + 1], x[q + 1], s1);
-                s2 = fma(-Ls[i][q + 2], x[q + 2], s2);
-                s3 = fma(-Ls[i][q + 3], x[q + 3], s3);
+                s0 = fma(-readlane_d(r[q], i), x[q], s0);
+                s1 = fma(-readlane_d(r[q + 1], i), x[q + 1], s1);
+                s2 = fma(-readlane_d(r[q + 2], i), x[q + 2], s2);
+                s3 = fma(-readlane_d(r[q + 3], i), x[q + 3], s3);
             }
 #pragma unroll
-            for (int q = i & ~3; q < i; ++q) s0 = fma(-Ls[i][q], x[q], s0);
-            x[i] = ((s0 + s1) + (s2 + s3)) / Ls[i][i];
+            for (int q = i & ~3; q < i; ++q) s0 = fma(-readlane_d(r[q], i), x[q], s0);
+            x[i] = ((s0 + s1) + (s2 + s3)) / readlane_d(r[i], i);
         } else {
             x[i] = 0.0;
         }
