@@ -87,7 +87,8 @@ typedef struct {
 
 /* Method parameters. ipm_params_default() fills the values used throughout:
  * sigma 0.5 (Section 7), gamma 0.9, theta 0.9999, tol_pcg 1e-10, gap_tol 1e-8,
- * min_step 1e-14, maxit_pcg 500, stag_window 10, stag_ratio 0.99, max_redraws 3, vcorr 1. */
+ * min_step 1e-14, maxit_pcg 500, stag_window 10, stag_ratio 0.99, max_redraws 3, vcorr 1,
+ * precision IPM_PLAIN, warm_start IPM_WARM_NONE, inner_tol 1e-4, max_refine 12. */
 typedef struct {
     double sigma;        /* centering parameter, in (0, 4/5) (Algorithm 3 input)            */
     double gamma;        /* neighbourhood parameter, in (0, 1)                              */
@@ -102,15 +103,33 @@ typedef struct {
     int32_t stag_window;
     int32_t max_redraws; /* extra draws of W (doubled w, s >= 2) after a failed solve      */
     int32_t vcorr;       /* 1: perturbation v of eq. compv; 0: v = 0                         */
+    int32_t precision;   /* IPM_PLAIN: FP64 accumulation everywhere. IPM_MIXED: the sketch
+                            accumulates in FP32 (B stored FP32) and CG runs as iterative
+                            refinement: inner CG with FP32-accumulated matvecs to inner_tol,
+                            outer residual p - A D^2 A^T dy recomputed with FP64 accumulation,
+                            stop on ||L^-1 r|| <= tol_pcg ||L^-1 p|| for that true residual     */
+    int32_t warm_start;  /* IPM_WARM_NONE | IPM_WARM_PREV (previous iteration's dy) |
+                            IPM_WARM_GIVEN (ipm_step_warm's dy0); kept only if its residual
+                            beats dy = 0                                                      */
+    double inner_tol;    /* relative tolerance of each inner CG solve (mixed form)           */
+    int32_t max_refine;  /* refinement rounds (mixed form)                                   */
+    int32_t reserved;
     uint64_t seed;       /* sketch seed                                                     */
 } ipm_params;
+
+#define IPM_PLAIN 0
+#define IPM_MIXED 1
+#define IPM_WARM_NONE 0
+#define IPM_WARM_PREV 1
+#define IPM_WARM_GIVEN 2
 
 typedef struct {
     int32_t iters;       /* CG iterations performed                                         */
     int32_t status;      /* IPM_OK, IPM_PCG_MAXIT, IPM_PCG_STAGNATED or IPM_ERR_BREAKDOWN    */
     int32_t warm_used;   /* 1 if the initial dy was kept (its residual beat dy = 0)          */
-    int32_t reserved;
-    double relres;       /* ||L^-1 r|| / ||L^-1 p|| at exit (recursive residual)             */
+    int32_t rounds;      /* refinement rounds (mixed form); 1 for the plain form             */
+    double relres;       /* ||L^-1 r|| / ||L^-1 p|| at exit: the recursive residual of the
+                            plain form, the FP64-recomputed true residual of the mixed form   */
     double rho_star;     /* ||L^-1 p||^2                                                     */
 } ipm_pcg_info;
 
@@ -124,6 +143,9 @@ typedef struct {
     double mu, gap, relgap, rp_rel, rd_rel, obj;   /* at the point before the step          */
     double alpha_max, alpha;                       /* Algorithm 3, steps 6-7                 */
     double pcg_relres, vnorm;
+    int32_t refine_rounds;     /* mixed form: outer refinement rounds                      */
+    int32_t warm_used;         /* 1 if the warm start was kept                              */
+    double dy_norm;            /* ||dy|| of the accepted direction                          */
 } ipm_step_info;
 
 /* ---- context ------------------------------------------------------------------------------ */
@@ -161,6 +183,9 @@ int ipm_precond_factor(ipm_ctx* ctx, int64_t m, int32_t w, int32_t b_dtype, cons
                        double* L, double* Linv, int64_t* bad_pivot);
 
 /* Preconditioned CG for A D^2 A^T dy = p with preconditioner Q = L L^T (Algorithm 1, step 3).
+ * params->precision selects the plain form (FP64 accumulation) or the mixed form (iterative
+ * refinement around FP32-accumulated inner solves, see ipm_params.precision); A's storage type
+ * is used as given in both.
  *   d2   [device] n doubles, the diagonal of D^2
  *   Linv [device] m x m lower triangle of L^{-1} (as written by ipm_precond_factor)
  *   p    [device] m doubles
@@ -186,6 +211,15 @@ int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const dou
 int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* params,
              ipm_step_info* info);
 
+/* ipm_step with an initial CG iterate dy0 [device, m doubles] (used when params->warm_start is
+ * IPM_WARM_GIVEN; e.g. the learned warm start). dy0 is read only. */
+int ipm_step_warm(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* params,
+                  const double* dy0, ipm_step_info* info);
+
+/* The accepted dy of the last successful ipm_step on this context [device, m doubles] is copied
+ * to out. Returns IPM_ERR_ARG if no step was taken yet or m differs. */
+int ipm_last_dy(ipm_ctx* ctx, int64_t m, double* out);
+
 /* ---- measurement ------------------------------------------------------------------------ */
 
 /* q = A diag(d2) A^T v in one pass over A (the CG matvec). v, q [device] m doubles;
@@ -193,10 +227,12 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
 int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v,
                       double* q);
 
-#define IPM_KERNEL_MATVEC  0   /* the CG matvec pass over A                               */
+#define IPM_KERNEL_MATVEC  0   /* the CG matvec pass over A (FP64 accumulation)           */
 #define IPM_KERNEL_SKETCH  1   /* the sketch pass over A                                  */
 #define IPM_KERNEL_GRAM    2   /* the Gram product B B^T                                  */
-#define IPM_KERNEL_COUNT   3
+#define IPM_KERNEL_MATVEC32 3  /* the mixed form's inner CG matvec (FP32 accumulation)   */
+#define IPM_KERNEL_RESID64 4   /* the mixed form's FP64-accumulated residual pass          */
+#define IPM_KERNEL_COUNT   5
 
 /* Enable (1) or disable (0) per-kernel timing with HIP events recorded around every launch of
  * the kernels above on the context's stream; enabling resets the totals. */

@@ -13,12 +13,14 @@ from dataclasses import dataclass, field
 from typing import Optional
 
 from . import native
-from .native import (IPM_BF16, IPM_CONVERGED, IPM_F32, IPM_F64, IPM_OK, IpmMatrix, IpmParams,
-                     IpmPcgInfo, IpmProblem, IpmState, IpmStepInfo)
+from .native import (IPM_BF16, IPM_CONVERGED, IPM_F32, IPM_F64, IPM_MIXED, IPM_OK, IPM_PLAIN,
+                     IPM_WARM_GIVEN, IPM_WARM_NONE, IPM_WARM_PREV, IpmMatrix, IpmParams, IpmPcgInfo,
+                     IpmProblem, IpmState, IpmStepInfo)
 
 __all__ = ["IpmError", "Context", "Matrix", "Problem", "State", "Params", "ipm_sketch",
-           "ipm_precond_factor", "ipm_pcg_solve", "ipm_step", "ipm_normal_matvec", "solve",
-           "IPM_OK", "IPM_CONVERGED", "IPM_F64", "IPM_F32", "IPM_BF16"]
+           "ipm_precond_factor", "ipm_pcg_solve", "ipm_step", "ipm_step_warm", "ipm_last_dy",
+           "ipm_normal_matvec", "solve", "IPM_OK", "IPM_CONVERGED", "IPM_F64", "IPM_F32", "IPM_BF16",
+           "IPM_PLAIN", "IPM_MIXED", "IPM_WARM_NONE", "IPM_WARM_PREV", "IPM_WARM_GIVEN"]
 
 
 def _torch():
@@ -183,11 +185,16 @@ class Params:
     stag_window: int = 10
     max_redraws: int = 3
     vcorr: int = 1
+    precision: int = IPM_PLAIN     # IPM_PLAIN or IPM_MIXED
+    warm_start: int = IPM_WARM_NONE
+    inner_tol: float = 1e-4
+    max_refine: int = 12
 
     def c(self) -> IpmParams:
         return IpmParams(self.sigma, self.gamma, self.theta, self.tol_pcg, self.gap_tol, self.min_step,
                          self.stag_ratio, self.w, self.s, self.maxit_pcg, self.stag_window, self.max_redraws,
-                         self.vcorr, self.seed & ((1 << 64) - 1))
+                         self.vcorr, self.precision, self.warm_start, self.inner_tol, self.max_refine, 0,
+                         self.seed & ((1 << 64) - 1))
 
 
 def ipm_normal_matvec(ctx: Context, A: Matrix, d2, v):
@@ -239,16 +246,40 @@ def ipm_pcg_solve(ctx: Context, A: Matrix, d2, Linv, p, params: Params, dy0=None
                                0 if dy0 is None else 1, ctypes.byref(prm), ctypes.byref(info))
     ctx.check(rc)
     return dy, {"iters": info.iters, "status": info.status, "warm_used": info.warm_used,
-                "relres": info.relres, "rho_star": info.rho_star}
+                "rounds": info.rounds, "relres": info.relres, "rho_star": info.rho_star}
 
 
 def ipm_step(ctx: Context, prob: Problem, st: State, params: Params) -> dict:
     """One iteration of Algorithm 3; updates st in place; returns the step info."""
+    return _step(ctx, prob, st, params, None)
+
+
+def ipm_step_warm(ctx: Context, prob: Problem, st: State, params: Params, dy0) -> dict:
+    """ipm_step with the initial CG iterate dy0 (device FP64, m); params.warm_start must be
+    IPM_WARM_GIVEN for dy0 to be used."""
+    torch = _torch()
+    _need_dev(dy0, "dy0", torch.float64)
+    return _step(ctx, prob, st, params, dy0)
+
+
+def ipm_last_dy(ctx: Context, m: int, device: int = 0):
+    """The dy accepted by the last successful step on ctx."""
+    torch = _torch()
+    out = torch.empty(m, dtype=torch.float64, device=f"cuda:{device}")
+    ctx.check(ctx.lib.ipm_last_dy(ctx.h, m, _ptr(out)))
+    return out
+
+
+def _step(ctx: Context, prob: Problem, st: State, params: Params, dy0) -> dict:
     pc = prob.c_struct()
     sc = IpmState(st.x.data_ptr(), st.y.data_ptr(), st.s.data_ptr(), st.k, st.mu0, st.r0norm)
     prm = params.c()
     info = IpmStepInfo()
-    rc = ctx.lib.ipm_step(ctx.h, ctypes.byref(pc), ctypes.byref(sc), ctypes.byref(prm), ctypes.byref(info))
+    if dy0 is None:
+        rc = ctx.lib.ipm_step(ctx.h, ctypes.byref(pc), ctypes.byref(sc), ctypes.byref(prm), ctypes.byref(info))
+    else:
+        rc = ctx.lib.ipm_step_warm(ctx.h, ctypes.byref(pc), ctypes.byref(sc), ctypes.byref(prm), _ptr(dy0),
+                                   ctypes.byref(info))
     st.k, st.mu0, st.r0norm = sc.k, sc.mu0, sc.r0norm
     d = info.as_dict()
     d["rc"] = rc

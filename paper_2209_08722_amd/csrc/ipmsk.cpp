@@ -22,7 +22,7 @@ namespace {
 enum WsId {
     W_PART = 0, W_COLPART, W_RED, W_D2, W_RD, W_DS, W_DX, W_RP, W_P, W_DY, W_RHAT, W_G1, W_G2, W_U, W_B,
     W_L, W_X, W_XT, W_T, W_SCAL, W_PCG_VEC, W_PCG_RHO, W_PCG_CD, W_PCG_CI, W_STATUS, W_PART3, W_PARTMIN,
-    W_INFO, W_GPART, W_SQ, W_COUNT
+    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_COUNT
 };
 
 struct TimedPair {
@@ -46,6 +46,8 @@ struct ipm_ctx {
     int64_t launches[IPM_KERNEL_COUNT] = {};
     std::vector<hipEvent_t> pool;
     int last_pcg_iters = 8;    // size of the first batch of queued CG iterations
+    int last_inner_iters = 8;  // the same for the inner solves of the mixed form
+    int64_t prev_m = 0;        // length of the accepted dy kept in W_PREV (0: none)
 };
 
 namespace {
@@ -266,13 +268,13 @@ int strip_buffers(ipm_ctx* ctx, const StripPlan& pl, int m, int nacc, StripCall*
     return IPM_OK;
 }
 
-// One matvec pass over A: out <- A diag(d2) A^T v.
+// One matvec pass over A: out <- A diag(d2) A^T v, accumulated in FP64 (acc64) or FP32.
 int matvec_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v, double* out,
-                const StripPlan& pl, const int* done, int tag) {
+                const StripPlan& pl, const int* done, int tag, int acc64 = 1) {
     StripCall c{};
     c.kind = STRIP_MATVEC;
     c.dtype = A->dtype;
-    c.acc64 = 1;
+    c.acc64 = acc64;
     c.post = POST_PLAIN;
     c.A = A->val;
     c.m = (int)A->m;
@@ -283,7 +285,32 @@ int matvec_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const doubl
     c.out0 = out;
     c.done = done;
     CHK(strip_buffers(ctx, pl, c.m, 1, &c));
-    Timer t(ctx, IPM_KERNEL_MATVEC, tag);
+    Timer t(ctx, acc64 || A->dtype == IPM_F64 ? IPM_KERNEL_MATVEC : IPM_KERNEL_MATVEC32, tag);
+    HIPCHK(launch_strip_pass(c, pl, ctx->stream));
+    t.stop();
+    HIPCHK(launch_strip_rowsum(c, pl, ctx->stream));
+    return IPM_OK;
+}
+
+// r <- p - A diag(d2) A^T dy with FP64 accumulation whatever the storage type of A (the true
+// residual of the refinement rounds).
+int resid_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* dy, const double* p, double* r,
+               const StripPlan& pl) {
+    StripCall c{};
+    c.kind = STRIP_MATVEC;
+    c.dtype = A->dtype;
+    c.acc64 = 1;
+    c.post = POST_RESP;
+    c.A = A->val;
+    c.m = (int)A->m;
+    c.n = A->n;
+    c.ld = A->ld;
+    c.vec0 = dy;
+    c.d2 = d2;
+    c.pvec = p;
+    c.out0 = r;
+    CHK(strip_buffers(ctx, pl, c.m, 1, &c));
+    Timer t(ctx, IPM_KERNEL_RESID64);
     HIPCHK(launch_strip_pass(c, pl, ctx->stream));
     t.stop();
     HIPCHK(launch_strip_rowsum(c, pl, ctx->stream));
@@ -291,18 +318,26 @@ int matvec_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const doubl
 }
 
 struct PcgOut {
-    int iters, status, warm_used;
+    int iters, status, warm_used, rounds;
     double relres, rho_star;
+};
+
+struct PcgCfg {
+    double tol;
+    int maxit;
+    int acc64;          // matvec accumulation: 1 FP64, 0 FP32 (low-precision storage only)
+    bool xt_ready;      // W_XT already holds X^T
+    int* last_iters;    // first batch size hint, updated with the count of this solve
 };
 
 // CG with preconditioner X^T X (X = L^{-1}); dy_out receives the solution.
 int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X, const double* p, double* dy_out,
-           int warm, const ipm_params* prm, PcgOut* out) {
+           int warm, const ipm_params* prm, const PcgCfg& cfg, PcgOut* out) {
     hipStream_t st = ctx->stream;
     const int m = (int)A->m;
     double* XT = nullptr;
     CHK(ws(ctx, W_XT, (size_t)m * m, &XT));
-    HIPCHK(launch_transpose(X, XT, m, st));
+    if (!cfg.xt_ready) HIPCHK(launch_transpose(X, XT, m, st));
     const StripPlan pl = strip_plan(A->dtype, m, A->n, ctx->num_cu, STRIP_MATVEC);
     if (pl.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
     double *vec = nullptr, *rho = nullptr, *cd = nullptr, *info = nullptr;
@@ -310,7 +345,7 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     CHK(ws(ctx, W_PCG_VEC, (size_t)8 * m, &vec));
     const int gb = gemv_blocks(m);
     CHK(ws(ctx, W_PCG_RHO, (size_t)2 * gb, &rho));
-    CHK(ws(ctx, W_PCG_CD, (size_t)PD_HIST + prm->maxit_pcg + 2, &cd));
+    CHK(ws(ctx, W_PCG_CD, (size_t)PD_HIST + cfg.maxit + 2, &cd));
     CHK(ws(ctx, W_PCG_CI, PI_COUNT, &ci));
     CHK(ws(ctx, W_INFO, 8, &info));
     PcgBufs b{};
@@ -330,29 +365,29 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     b.n_rho = gb;
     b.cd = cd;
     b.ci = ci;
-    b.tol = prm->tol_pcg;
+    b.tol = cfg.tol;
     b.stag_ratio = prm->stag_ratio;
     b.stag_window = prm->stag_window;
-    b.maxit = prm->maxit_pcg;
+    b.maxit = cfg.maxit;
     HIPCHK(launch_fill_i32(ci, PI_COUNT, 0, st));
-    if (warm) CHK(matvec_pass(ctx, A, d2, dy_out, b.q, pl, nullptr, -1));
+    if (warm) CHK(matvec_pass(ctx, A, d2, dy_out, b.q, pl, nullptr, -1, cfg.acc64));
     HIPCHK(launch_pcg_init1(b, warm, st));
     HIPCHK(launch_pcg_init2(b, warm, dy_out, st));
     int* hi = reinterpret_cast<int*>(ctx->pinned);
     int j = 0;
     // first batch: the previous solve's iteration count (CG counts change slowly between IPM
     // iterations); later batches are short so that few no-op launches follow the stop
-    int batch = ctx->last_pcg_iters > 4 ? ctx->last_pcg_iters : 4;
+    int batch = *cfg.last_iters > 4 ? *cfg.last_iters : 4;
     const int* done = ci + PI_DONE;
     for (;;) {
-        for (int t = 0; t < batch && j < prm->maxit_pcg; ++t, ++j) {
-            CHK(matvec_pass(ctx, A, d2, b.dv, b.q, pl, done, j));
+        for (int t = 0; t < batch && j < cfg.maxit; ++t, ++j) {
+            CHK(matvec_pass(ctx, A, d2, b.dv, b.q, pl, done, j, cfg.acc64));
             HIPCHK(launch_pcg_gemv1(b, j, st));
             HIPCHK(launch_pcg_gemv2(b, j, st));
         }
         HIPCHK(hipMemcpyAsync(hi, ci, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (hi[PI_DONE] || j >= prm->maxit_pcg) break;
+        if (hi[PI_DONE] || j >= cfg.maxit) break;
         batch = 4;
     }
     HIPCHK(launch_pcg_finish(b, dy_out, info, st));
@@ -364,9 +399,125 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     out->warm_used = (int)hd[2];
     out->relres = hd[3];
     out->rho_star = hd[4];
-    ctx->last_pcg_iters = out->iters;
+    out->rounds = 1;
+    *cfg.last_iters = out->iters;
     resolve_timing(ctx, IPM_KERNEL_MATVEC, out->iters);
+    resolve_timing(ctx, IPM_KERNEL_MATVEC32, out->iters);
     resolve_timing(ctx, IPM_KERNEL_SKETCH, INT_MAX);
+    return IPM_OK;
+}
+
+// ||X v||^2 into *out (device): two launches, no host synchronization.
+int precond_norm2(ipm_ctx* ctx, const double* X, int m, const double* v, double* g, double* out) {
+    HIPCHK(launch_trigemv(X, m, 1, v, g, ctx->stream));
+    HIPCHK(launch_dot(m, g, g, out, ctx->stream));
+    return IPM_OK;
+}
+
+// Mixed form of the CG solve: iterative refinement. Each round solves M delta = r with inner CG
+// whose matvecs read the low-precision A and accumulate in FP32, to the relative tolerance
+// inner_tol; then dy += delta and r = p - M dy is recomputed with FP64 accumulation. The stop test
+// is the plain method's, ||L^{-1} r|| <= tol_pcg ||L^{-1} p||, on that recomputed residual. A round
+// that does not shrink the residual by half (FP32 accumulation error comparable to the
+// preconditioned system's scale, late in the IPM) switches the inner solves to FP64 accumulation.
+int do_pcg_mixed(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X, const double* p,
+                 double* dy, const double* dy0, const ipm_params* prm, PcgOut* out) {
+    hipStream_t st = ctx->stream;
+    const int m = (int)A->m;
+    const StripPlan pl = strip_plan(A->dtype, m, A->n, ctx->num_cu, STRIP_MATVEC);
+    if (pl.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
+    double *ref = nullptr, *XT = nullptr;
+    CHK(ws(ctx, W_REF, (size_t)4 * m + 8, &ref));
+    CHK(ws(ctx, W_XT, (size_t)m * m, &XT));
+    double* r = ref;             // true residual p - M dy
+    double* delta = ref + m;     // inner solution
+    double* g = ref + 2 * m;     // X v
+    double* sc = ref + 4 * m;    // [0] ||X p||^2, [1] ||X r||^2, [2] ||X r0||^2 (warm start)
+    double* hd = reinterpret_cast<double*>(ctx->pinned) + 64;
+    HIPCHK(launch_transpose(X, XT, m, st));
+    CHK(precond_norm2(ctx, X, m, p, g, sc));
+    out->warm_used = 0;
+    if (dy0) {
+        CHK(resid_pass(ctx, A, d2, dy0, p, r, pl));
+        CHK(precond_norm2(ctx, X, m, r, g, sc + 2));
+        HIPCHK(hipMemcpyAsync(hd, sc, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        out->warm_used = hd[2] < hd[0] ? 1 : 0;
+    }
+    if (out->warm_used) {
+        HIPCHK(hipMemcpyAsync(dy, dy0, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    } else {
+        HIPCHK(launch_fill(dy, m, 0.0, st));
+        HIPCHK(hipMemcpyAsync(r, p, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    }
+    bool fp64_inner = A->dtype == IPM_F64;
+    int total = 0, rounds = 0, status = IPM_PCG_MAXIT;
+    double rn_prev = -1.0, pn = 0.0, rn = 0.0;
+    for (;;) {
+        CHK(precond_norm2(ctx, X, m, r, g, sc + 1));
+        HIPCHK(hipMemcpyAsync(hd, sc, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        pn = std::sqrt(hd[0]);
+        rn = std::sqrt(hd[1]);
+        if (!is_finite(rn)) {
+            status = IPM_ERR_BREAKDOWN;
+            break;
+        }
+        if (rn <= prm->tol_pcg * pn) {
+            status = IPM_OK;
+            break;
+        }
+        if (rounds >= prm->max_refine || total >= prm->maxit_pcg) break;
+        if (rn_prev > 0.0 && rn > 0.5 * rn_prev) {
+            if (fp64_inner) {   // no progress even with FP64 accumulation
+                status = IPM_PCG_STAGNATED;
+                break;
+            }
+            fp64_inner = true;
+        }
+        rn_prev = rn;
+        // FP64 rounds aim at the final tolerance directly; FP32 rounds at inner_tol
+        const double need = 0.5 * prm->tol_pcg * pn / rn;
+        PcgCfg cfg{};
+        cfg.tol = fp64_inner ? need : (need > prm->inner_tol ? need : prm->inner_tol);
+        cfg.maxit = prm->maxit_pcg - total;
+        cfg.acc64 = fp64_inner ? 1 : 0;
+        cfg.xt_ready = true;
+        cfg.last_iters = fp64_inner ? &ctx->last_pcg_iters : &ctx->last_inner_iters;
+        PcgOut io{};
+        CHK(do_pcg(ctx, A, d2, X, r, delta, 0, prm, cfg, &io));
+        total += io.iters;
+        ++rounds;
+        if (io.status == IPM_ERR_BREAKDOWN) {
+            if (fp64_inner) {
+                status = IPM_ERR_BREAKDOWN;
+                break;
+            }
+            fp64_inner = true;
+            continue;
+        }
+        HIPCHK(launch_axpy(m, 1.0, delta, dy, st));
+        CHK(resid_pass(ctx, A, d2, dy, p, r, pl));
+    }
+    out->iters = total;
+    out->rounds = rounds;
+    out->status = status;
+    out->relres = pn > 0.0 ? rn / pn : 0.0;
+    out->rho_star = pn * pn;
+    resolve_timing(ctx, IPM_KERNEL_RESID64, INT_MAX);
+    return IPM_OK;
+}
+
+// The parameters of the CG solve alone (ipm_pcg_solve).
+int check_solver_params(ipm_ctx* ctx, const ipm_params* p) {
+    if (p->maxit_pcg < 1 || p->maxit_pcg > 100000) return fail(ctx, IPM_ERR_ARG, "maxit_pcg out of range");
+    if (p->stag_window < 1) return fail(ctx, IPM_ERR_ARG, "stag_window must be >= 1");
+    if (!(p->tol_pcg >= 0 && is_finite(p->tol_pcg))) return fail(ctx, IPM_ERR_ARG, "bad tol_pcg");
+    if (!(p->stag_ratio > 0 && is_finite(p->stag_ratio))) return fail(ctx, IPM_ERR_ARG, "bad stag_ratio");
+    if (p->precision != IPM_PLAIN && p->precision != IPM_MIXED) return fail(ctx, IPM_ERR_ARG, "bad precision");
+    if (p->warm_start < IPM_WARM_NONE || p->warm_start > IPM_WARM_GIVEN) return fail(ctx, IPM_ERR_ARG, "bad warm_start");
+    if (!(p->inner_tol > 0 && p->inner_tol < 1)) return fail(ctx, IPM_ERR_ARG, "inner_tol must be in (0, 1)");
+    if (p->max_refine < 1 || p->max_refine > 1000) return fail(ctx, IPM_ERR_ARG, "max_refine out of range");
     return IPM_OK;
 }
 
@@ -385,7 +536,7 @@ int check_params(ipm_ctx* ctx, const ipm_params* p, int64_t m) {
     if (p->s < 1 || p->s > 8) return fail(ctx, IPM_ERR_ARG, "s must be in 1..8");
     if (p->w < 1 || p->w % p->s != 0) return fail(ctx, IPM_ERR_ARG, "s must divide w");
     if (p->w < m) return fail(ctx, IPM_ERR_ARG, "w (%d) must be >= m (%lld)", p->w, (long long)m);
-    return IPM_OK;
+    return check_solver_params(ctx, p);
 }
 
 }  // namespace
@@ -408,6 +559,10 @@ void ipm_params_default(ipm_params* p) {
     p->stag_window = 10;
     p->max_redraws = 3;
     p->vcorr = 1;
+    p->precision = IPM_PLAIN;
+    p->warm_start = IPM_WARM_NONE;
+    p->inner_tol = 1e-4;
+    p->max_refine = 12;
     p->seed = 0;
 }
 
@@ -512,16 +667,28 @@ int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const dou
     if (!ctx) return IPM_ERR_ARG;
     CHK(check_matrix(ctx, A));
     if (!d2 || !Linv || !p || !dy || !params) return fail(ctx, IPM_ERR_ARG, "null pointer");
-    if (params->maxit_pcg < 1 || params->stag_window < 1 || !(params->tol_pcg >= 0))
-        return fail(ctx, IPM_ERR_ARG, "bad CG parameters");
+    CHK(check_solver_params(ctx, params));
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
     PcgOut o{};
-    CHK(do_pcg(ctx, A, d2, Linv, p, dy, warm ? 1 : 0, params, &o));
+    if (params->precision == IPM_MIXED) {
+        const int m = (int)A->m;
+        const double* dy0 = nullptr;
+        if (warm) {
+            double* w0 = nullptr;
+            CHK(ws(ctx, W_WARM, (size_t)m, &w0));
+            HIPCHK(hipMemcpyAsync(w0, dy, sizeof(double) * m, hipMemcpyDeviceToDevice, ctx->stream));
+            dy0 = w0;
+        }
+        CHK(do_pcg_mixed(ctx, A, d2, Linv, p, dy, dy0, params, &o));
+    } else {
+        PcgCfg cfg{params->tol_pcg, params->maxit_pcg, 1, false, &ctx->last_pcg_iters};
+        CHK(do_pcg(ctx, A, d2, Linv, p, dy, warm ? 1 : 0, params, cfg, &o));
+    }
     if (info) {
         info->iters = o.iters;
         info->status = o.status;
         info->warm_used = o.warm_used;
-        info->reserved = 0;
+        info->rounds = o.rounds;
         info->relres = o.relres;
         info->rho_star = o.rho_star;
     }
@@ -541,7 +708,12 @@ int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const
     return IPM_OK;
 }
 
-int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* prm, ipm_step_info* info) {
+}  // extern "C"
+
+namespace {
+
+int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* prm, const double* dy_given,
+              ipm_step_info* info) {
     if (!ctx) return IPM_ERR_ARG;
     if (!prob || !state || !info) return fail(ctx, IPM_ERR_ARG, "null pointer");
     std::memset(info, 0, sizeof(*info));
@@ -549,9 +721,12 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
     CHK(check_matrix(ctx, A));
     CHK(check_params(ctx, prm, A->m));
     if (!prob->b || !prob->c || !state->x || !state->y || !state->s) return fail(ctx, IPM_ERR_ARG, "null vector");
+    if (prm->warm_start == IPM_WARM_GIVEN && !dy_given)
+        return fail(ctx, IPM_ERR_ARG, "warm_start IPM_WARM_GIVEN needs ipm_step_warm's dy0");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
     hipStream_t st = ctx->stream;
     const int m = (int)A->m;
+    const bool mixed = prm->precision == IPM_MIXED;
     const int64_t n = A->n;
     const int Gn = pointwise_blocks(n);
 
@@ -624,10 +799,27 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
         return IPM_CONVERGED;
     }
 
-    // Algorithm 1 with redraws of W: sketch, factor, CG
+    // initial CG iterate: the previous accepted dy or the caller's, the same for every draw
+    const double* dy0 = nullptr;
+    if (prm->warm_start == IPM_WARM_GIVEN) {
+        dy0 = dy_given;
+    } else if (prm->warm_start == IPM_WARM_PREV && ctx->prev_m == m) {
+        dy0 = reinterpret_cast<const double*>(ctx->ws[W_PREV]);
+    }
+
+    // Algorithm 1 with redraws of W: sketch, factor, CG. The mixed form keeps B in FP32.
     const int wmax = prm->w << prm->max_redraws;
-    double *B = nullptr, *Lw = nullptr, *X = nullptr;
-    CHK(ws(ctx, W_B, (size_t)m * (size_t)wmax, &B));
+    void* B = nullptr;
+    double *Lw = nullptr, *X = nullptr;
+    if (mixed) {
+        float* Bf = nullptr;
+        CHK(ws(ctx, W_BF, (size_t)m * (size_t)wmax, &Bf));
+        B = Bf;
+    } else {
+        double* Bd = nullptr;
+        CHK(ws(ctx, W_B, (size_t)m * (size_t)wmax, &Bd));
+        B = Bd;
+    }
     CHK(ws(ctx, W_L, (size_t)m * m, &Lw));
     CHK(ws(ctx, W_X, (size_t)m * m, &X));
     HashKeys hk{};
@@ -640,9 +832,9 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
         s_used = a == 0 ? prm->s : (prm->s > 2 ? prm->s : 2);
         const uint64_t seed_a = a == 0 ? prm->seed : prm->seed + (uint64_t)a * 0x632BE59BD9B4E019ull;
         hk = make_keys(seed_a, state->k, w_used, s_used);
-        CHK(do_sketch(ctx, A, d2, 1, hk, w_used, 1, B));
+        CHK(do_sketch(ctx, A, d2, 1, hk, w_used, mixed ? 0 : 1, B));
         int64_t bad = -1;
-        CHK(do_factor(ctx, m, w_used, 1, B, Lw, X, &bad));
+        CHK(do_factor(ctx, m, w_used, mixed ? 0 : 1, B, Lw, X, &bad));
         if (bad >= 0) {
             if (a == prm->max_redraws) {
                 info->attempts = attempts;
@@ -651,7 +843,13 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
             }
             continue;
         }
-        CHK(do_pcg(ctx, A, d2, X, p, dyv, 0, prm, &po));
+        if (mixed) {
+            CHK(do_pcg_mixed(ctx, A, d2, X, p, dyv, dy0, prm, &po));
+        } else {
+            if (dy0) HIPCHK(hipMemcpyAsync(dyv, dy0, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+            PcgCfg cfg{prm->tol_pcg, prm->maxit_pcg, 1, false, &ctx->last_pcg_iters};
+            CHK(do_pcg(ctx, A, d2, X, p, dyv, dy0 ? 1 : 0, prm, cfg, &po));
+        }
         if (po.status == IPM_ERR_BREAKDOWN) {
             info->status = IPM_ERR_BREAKDOWN;
             return fail(ctx, IPM_ERR_BREAKDOWN, "CG breakdown");
@@ -664,6 +862,8 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
     info->pcg_iters = po.iters;
     info->pcg_status = po.status;
     info->pcg_relres = po.relres;
+    info->refine_rounds = po.rounds;
+    info->warm_used = po.warm_used;
 
     // directions (eq. ipm_inf): ds, true residual, v, dx
     {
@@ -693,15 +893,18 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
         CHK(ws(ctx, W_XT, (size_t)m * m, &XT));   // written by do_pcg for this draw
         HIPCHK(launch_trigemv(X, m, 1, rhat, g1, st));
         HIPCHK(launch_trigemv(XT, m, 0, g1, g2, st));
-        HIPCHK(launch_btg(B, 1, m, w_used, g2, u, st));
+        HIPCHK(launch_btg(B, mixed ? 0 : 1, m, w_used, g2, u, st));
     }
     HIPCHK(launch_dx(n, state->x, state->s, d2, ds, u, prm->vcorr, hk, scal, dx, part3, st));
     HIPCHK(launch_fin_dx(part3, Gn, scal, st));
     HIPCHK(launch_roots(n, state->x, state->s, dx, ds, prm->gamma, scal, partmin, st));
     HIPCHK(launch_alpha(n, partmin, Gn, prm->gamma, prm->theta, prm->min_step, scal, st));
     HIPCHK(launch_update(n, m, state->x, state->y, state->s, dx, dyv, ds, scal, st));
+    HIPCHK(launch_dot(m, dyv, dyv, sq + 2, st));
     HIPCHK(hipMemcpyAsync(hs, scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hs + SC_COUNT, sq + 2, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    info->dy_norm = std::sqrt(hs[SC_COUNT]);
     info->alpha_max = hs[SC_AMAX];
     info->alpha = hs[SC_ABAR];
     info->vnorm = std::sqrt(hs[SC_V2]);
@@ -710,8 +913,37 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
         return fail(ctx, IPM_ERR_STALL, "step length %.3e below min_step", info->alpha);
     }
     state->k += 1;
+    double* prev = nullptr;
+    CHK(ws(ctx, W_PREV, (size_t)m, &prev));
+    HIPCHK(hipMemcpyAsync(prev, dyv, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    ctx->prev_m = m;
     info->status = po.status;
     return po.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* prm, ipm_step_info* info) {
+    return step_impl(ctx, prob, state, prm, nullptr, info);
+}
+
+int ipm_step_warm(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* prm, const double* dy0,
+                  ipm_step_info* info) {
+    if (!ctx) return IPM_ERR_ARG;
+    if (!dy0) return fail(ctx, IPM_ERR_ARG, "dy0 is null");
+    return step_impl(ctx, prob, state, prm, dy0, info);
+}
+
+int ipm_last_dy(ipm_ctx* ctx, int64_t m, double* out) {
+    if (!ctx) return IPM_ERR_ARG;
+    if (!out) return fail(ctx, IPM_ERR_ARG, "out is null");
+    if (ctx->prev_m == 0 || ctx->prev_m != m) return fail(ctx, IPM_ERR_ARG, "no accepted dy of length %lld", (long long)m);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    HIPCHK(hipMemcpyAsync(out, ctx->ws[W_PREV], sizeof(double) * m, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return IPM_OK;
 }
 
 }  // extern "C"

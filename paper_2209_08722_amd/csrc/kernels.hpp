@@ -13,7 +13,7 @@ enum Scalar {
 };
 
 // Post-processing of the row reduction of strip-pass partials.
-enum RowPost { POST_PLAIN = 0, POST_MATVEC = 1, POST_RESID = 2, POST_RHAT = 3 };
+enum RowPost { POST_PLAIN = 0, POST_MATVEC = 1, POST_RESID = 2, POST_RHAT = 3, POST_RESP = 4 };
 
 // Kinds of single-pass strip kernels over row-major A.
 enum StripKind { STRIP_MATVEC = 0, STRIP_RESID = 1, STRIP_DIR = 2 };
@@ -140,5 +140,8 @@ hipError_t launch_alpha(int64_t n, const double* partmin, int G, double gamma, d
                         double min_step, double* scal, hipStream_t st);
 hipError_t launch_update(int64_t n, int m, double* x, double* y, double* s, const double* dx,
                          const double* dy, const double* ds, const double* scal, hipStream_t st);
+// y += alpha * x (m-vectors); out[0] = x^T y (one block).
+hipError_t launch_axpy(int m, double alpha, const double* x, double* y, hipStream_t st);
+hipError_t launch_dot(int m, const double* x, const double* y, double* out, hipStream_t st);
 
 }  // namespace ipmsk

@@ -176,7 +176,34 @@ __global__ __launch_bounds__(PNT) void k_update(int64_t n, int m, double* __rest
     for (int64_t i = (int64_t)blockIdx.x * PNT + threadIdx.x; i < m; i += (int64_t)gridDim.x * PNT) y[i] += a * dy[i];
 }
 
+__global__ __launch_bounds__(PNT) void k_axpy(int m, double alpha, const double* __restrict__ x,
+                                              double* __restrict__ y) {
+    for (int i = blockIdx.x * PNT + threadIdx.x; i < m; i += gridDim.x * PNT) y[i] += alpha * x[i];
+}
+
+__global__ __launch_bounds__(PNT) void k_dot(int m, const double* __restrict__ x, const double* __restrict__ y,
+                                             double* __restrict__ out) {
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < m; i += PNT) s += x[i] * y[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
 }  // namespace
+
+hipError_t launch_axpy(int m, double alpha, const double* x, double* y, hipStream_t st) {
+    int g = (m + PNT - 1) / PNT;
+    if (g > 64) g = 64;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_axpy, dim3(g), dim3(PNT), 0, st, m, alpha, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(int m, const double* x, const double* y, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot, dim3(1), dim3(PNT), 0, st, m, x, y, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_stats(int64_t n, const double* x, const double* s, const double* c, double* d2, double* part3,
                         hipStream_t st) {

@@ -99,6 +99,7 @@ __global__ __launch_bounds__(RNT) void k_rowsum(StripCall a, int G, int nacc, in
                     break;
                 }
                 case POST_RHAT: a.out0[i] = t0 - a.pvec[i]; break;
+                case POST_RESP: a.out0[i] = a.pvec[i] - t0; break;
                 default: break;
             }
         }

@@ -27,7 +27,9 @@ IPM_ERR_NOMEM = -6
 
 IPM_F64, IPM_F32, IPM_BF16 = 0, 1, 2
 IPM_DENSE_ROWMAJOR = 0
-IPM_KERNEL_MATVEC, IPM_KERNEL_SKETCH, IPM_KERNEL_GRAM = 0, 1, 2
+IPM_KERNEL_MATVEC, IPM_KERNEL_SKETCH, IPM_KERNEL_GRAM, IPM_KERNEL_MATVEC32, IPM_KERNEL_RESID64 = 0, 1, 2, 3, 4
+IPM_PLAIN, IPM_MIXED = 0, 1
+IPM_WARM_NONE, IPM_WARM_PREV, IPM_WARM_GIVEN = 0, 1, 2
 
 STATUS_NAMES = {
     IPM_OK: "IPM_OK", IPM_CONVERGED: "IPM_CONVERGED", IPM_PCG_MAXIT: "IPM_PCG_MAXIT",
@@ -55,11 +57,12 @@ class IpmParams(ctypes.Structure):
     _fields_ = [("sigma", c_double), ("gamma", c_double), ("theta", c_double), ("tol_pcg", c_double),
                 ("gap_tol", c_double), ("min_step", c_double), ("stag_ratio", c_double),
                 ("w", c_int32), ("s", c_int32), ("maxit_pcg", c_int32), ("stag_window", c_int32),
-                ("max_redraws", c_int32), ("vcorr", c_int32), ("seed", c_uint64)]
+                ("max_redraws", c_int32), ("vcorr", c_int32), ("precision", c_int32), ("warm_start", c_int32),
+                ("inner_tol", c_double), ("max_refine", c_int32), ("reserved", c_int32), ("seed", c_uint64)]
 
 
 class IpmPcgInfo(ctypes.Structure):
-    _fields_ = [("iters", c_int32), ("status", c_int32), ("warm_used", c_int32), ("reserved", c_int32),
+    _fields_ = [("iters", c_int32), ("status", c_int32), ("warm_used", c_int32), ("rounds", c_int32),
                 ("relres", c_double), ("rho_star", c_double)]
 
 
@@ -68,7 +71,8 @@ class IpmStepInfo(ctypes.Structure):
                 ("k", c_int64), ("w_used", c_int32), ("s_used", c_int32),
                 ("mu", c_double), ("gap", c_double), ("relgap", c_double), ("rp_rel", c_double),
                 ("rd_rel", c_double), ("obj", c_double), ("alpha_max", c_double), ("alpha", c_double),
-                ("pcg_relres", c_double), ("vnorm", c_double)]
+                ("pcg_relres", c_double), ("vnorm", c_double), ("refine_rounds", c_int32), ("warm_used", c_int32),
+                ("dy_norm", c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -89,6 +93,9 @@ SIGNATURES = [
                               POINTER(IpmParams), POINTER(IpmPcgInfo)]),
     ("ipm_step", c_int, [c_void_p, POINTER(IpmProblem), POINTER(IpmState), POINTER(IpmParams),
                          POINTER(IpmStepInfo)]),
+    ("ipm_step_warm", c_int, [c_void_p, POINTER(IpmProblem), POINTER(IpmState), POINTER(IpmParams), c_void_p,
+                              POINTER(IpmStepInfo)]),
+    ("ipm_last_dy", c_int, [c_void_p, c_int64, c_void_p]),
     ("ipm_normal_matvec", c_int, [c_void_p, POINTER(IpmMatrix), c_void_p, c_void_p, c_void_p]),
     ("ipm_ctx_set_timing", c_int, [c_void_p, c_int32]),
     ("ipm_kernel_time", c_int, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]),

@@ -40,15 +40,35 @@ def test_binding_signatures_cover_the_header():
     assert set(declared_functions()) <= bound
 
 
-def test_struct_layouts_match_header():
-    """ctypes mirrors of the C structs have the sizes the C compiler gives them."""
+STRUCTS = {"IpmMatrix": "ipm_matrix", "IpmProblem": "ipm_problem", "IpmState": "ipm_state",
+           "IpmParams": "ipm_params", "IpmPcgInfo": "ipm_pcg_info", "IpmStepInfo": "ipm_step_info"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the C structs have the size and field offsets the C compiler gives them."""
+    import shutil
+    import subprocess
     from paper_2209_08722_amd import native
-    assert ctypes.sizeof(native.IpmMatrix) == 40
-    assert ctypes.sizeof(native.IpmProblem) == 56
-    assert ctypes.sizeof(native.IpmState) == 48
-    assert ctypes.sizeof(native.IpmParams) == 7 * 8 + 6 * 4 + 8
-    assert ctypes.sizeof(native.IpmPcgInfo) == 32
-    assert ctypes.sizeof(native.IpmStepInfo) == 4 * 4 + 8 + 2 * 4 + 10 * 8
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ipmsk.h"', "int main(void) {"]
+    expect = []
+    for py, cname in STRUCTS.items():
+        cls = getattr(native, py)
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(cls))
+        for fname, _ in cls._fields_:
+            if fname == "reserved":
+                continue
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {fname}));')
+            expect.append(getattr(cls, fname).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == expect
 
 
 def test_product_path_does_not_import_the_oracle():
