@@ -109,8 +109,10 @@ typedef struct {
                             outer residual p - A D^2 A^T dy recomputed with FP64 accumulation,
                             stop on ||L^-1 r|| <= tol_pcg ||L^-1 p|| for that true residual     */
     int32_t warm_start;  /* IPM_WARM_NONE | IPM_WARM_PREV (previous iteration's dy) |
-                            IPM_WARM_GIVEN (ipm_step_warm's dy0); kept only if its residual
-                            beats dy = 0                                                      */
+                            IPM_WARM_GIVEN (ipm_step_warm's dy0). The initial iterate is
+                            beta dy0 with beta = dy0^T p / dy0^T M dy0 (the multiple of dy0
+                            closest to the solution in the M-norm), kept only if its
+                            preconditioned residual beats that of dy = 0                      */
     double inner_tol;    /* relative tolerance of each inner CG solve (mixed form)           */
     int32_t max_refine;  /* refinement rounds (mixed form)                                   */
     int32_t reserved;
@@ -189,8 +191,9 @@ int ipm_precond_factor(ipm_ctx* ctx, int64_t m, int32_t w, int32_t b_dtype, cons
  *   d2   [device] n doubles, the diagonal of D^2
  *   Linv [device] m x m lower triangle of L^{-1} (as written by ipm_precond_factor)
  *   p    [device] m doubles
- *   dy   [device] m doubles; input: initial iterate if warm != 0 (kept only if its
- *        preconditioned residual is below that of 0), output: the solution.
+ *   dy   [device] m doubles; input: initial iterate dy0 if warm != 0 (scaled to beta dy0,
+ *        beta = dy0^T p / dy0^T M dy0, and kept only if its preconditioned residual is below
+ *        that of 0), output: the solution.
  *   Stops when ||L^-1 (p - A D^2 A^T dy)|| <= tol_pcg * ||L^-1 p|| (eq. pdcond2), at maxit_pcg,
  *   or when the residual stagnates (params stag_window / stag_ratio). Synchronizes. */
 int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* Linv,

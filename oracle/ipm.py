@@ -160,7 +160,13 @@ def pcg(matvec: Callable, L: np.ndarray, p: np.ndarray, tol: float, maxit: int,
 
     ``matvec(v)`` applies M = A D^2 A^T. The residual norm reported is the
     paper's ||f|| = ||Q^{-1/2}(M dy - p)|| = ||L^{-1} r|| (Section 3.1).
-    A warm start dy0 is used only if its residual is smaller than that of 0.
+
+    Warm start (not in the paper): dy0 is first scaled by the factor
+    beta = dy0^T p / dy0^T M dy0 that minimises the M-norm error
+    ||dy* - beta dy0||_M (a one-dimensional Galerkin projection; beta = 0 if
+    dy0^T M dy0 <= 0). The scaled iterate is kept only if its preconditioned
+    residual is smaller than that of 0, so the stop test, relative to
+    ||L^{-1} p||, is unchanged.
     """
     def lsolve(r):
         return sla.solve_triangular(L, r, lower=True)
@@ -176,10 +182,13 @@ def pcg(matvec: Callable, L: np.ndarray, p: np.ndarray, tol: float, maxit: int,
     wv = wp
     warm_used = False
     if dy0 is not None:
-        r0 = p - matvec(dy0)
+        q0 = matvec(dy0)
+        den = float(dy0 @ q0)
+        beta = float(dy0 @ p) / den if den > 0.0 else 0.0
+        r0 = p - beta * q0
         w0 = lsolve(r0)
         if float(w0 @ w0) < rho_star:
-            dy, r, wv, warm_used = dy0.copy(), r0, w0, True
+            dy, r, wv, warm_used = beta * dy0, r0, w0, True
     rho = float(wv @ wv)
     hist = [np.sqrt(rho)]
     thresh = tol * np.sqrt(rho_star)

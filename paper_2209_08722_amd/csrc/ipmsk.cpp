@@ -370,7 +370,10 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     b.stag_window = prm->stag_window;
     b.maxit = cfg.maxit;
     HIPCHK(launch_fill_i32(ci, PI_COUNT, 0, st));
-    if (warm) CHK(matvec_pass(ctx, A, d2, dy_out, b.q, pl, nullptr, -1, cfg.acc64));
+    if (warm) {
+        CHK(matvec_pass(ctx, A, d2, dy_out, b.q, pl, nullptr, -1, cfg.acc64));
+        HIPCHK(launch_warm_scale(m, dy_out, p, b.q, dy_out, nullptr, st));
+    }
     HIPCHK(launch_pcg_init1(b, warm, st));
     HIPCHK(launch_pcg_init2(b, warm, dy_out, st));
     int* hi = reinterpret_cast<int*>(ctx->pinned);
@@ -430,22 +433,25 @@ int do_pcg_mixed(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const doub
     CHK(ws(ctx, W_REF, (size_t)4 * m + 8, &ref));
     CHK(ws(ctx, W_XT, (size_t)m * m, &XT));
     double* r = ref;             // true residual p - M dy
-    double* delta = ref + m;     // inner solution
+    double* delta = ref + m;     // inner solution (and M dy0 for the warm start)
     double* g = ref + 2 * m;     // X v
+    double* dyw = ref + 3 * m;   // scaled warm start
     double* sc = ref + 4 * m;    // [0] ||X p||^2, [1] ||X r||^2, [2] ||X r0||^2 (warm start)
     double* hd = reinterpret_cast<double*>(ctx->pinned) + 64;
     HIPCHK(launch_transpose(X, XT, m, st));
     CHK(precond_norm2(ctx, X, m, p, g, sc));
     out->warm_used = 0;
     if (dy0) {
-        CHK(resid_pass(ctx, A, d2, dy0, p, r, pl));
+        // energy-optimal multiple of dy0 and its residual, both with FP64 accumulation
+        CHK(matvec_pass(ctx, A, d2, dy0, delta, pl, nullptr, -1, 1));
+        HIPCHK(launch_warm_scale(m, dy0, p, delta, dyw, r, st));
         CHK(precond_norm2(ctx, X, m, r, g, sc + 2));
         HIPCHK(hipMemcpyAsync(hd, sc, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         out->warm_used = hd[2] < hd[0] ? 1 : 0;
     }
     if (out->warm_used) {
-        HIPCHK(hipMemcpyAsync(dy, dy0, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(dy, dyw, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
     } else {
         HIPCHK(launch_fill(dy, m, 0.0, st));
         HIPCHK(hipMemcpyAsync(r, p, sizeof(double) * m, hipMemcpyDeviceToDevice, st));

@@ -123,6 +123,8 @@ hipError_t launch_pcg_init2(const PcgBufs& b, int warm, const double* dy_in, hip
 hipError_t launch_pcg_gemv1(const PcgBufs& b, int j, hipStream_t st);
 hipError_t launch_pcg_gemv2(const PcgBufs& b, int j, hipStream_t st);
 hipError_t launch_pcg_finish(const PcgBufs& b, double* dy_out, double* info_out, hipStream_t st);
+hipError_t launch_warm_scale(int m, const double* dy0, const double* p, double* q, double* dy_out, double* r_out,
+                             hipStream_t st);
 // y = L^{-1} x (lower) or (L^{-1})^T x (upper, given XT) - plain triangular GEMV.
 hipError_t launch_trigemv(const double* M, int m, int lower, const double* xin, double* yout, hipStream_t st);
 

@@ -86,6 +86,28 @@ __device__ __forceinline__ double finish_upper(const double* __restrict__ M, int
     return wave_sum(acc);
 }
 
+// Warm start scaling: beta = dy0^T p / dy0^T q with q = M dy0 minimises ||dy* - beta dy0||_M
+// (beta = 0 when dy0^T q <= 0). Scales q in place, writes beta dy0 (dy_out may alias dy0) and,
+// if r_out is given, r_out = p - beta q. One block: the vectors have m entries.
+__global__ __launch_bounds__(GNT) void k_warm_scale(int m, const double* dy0, const double* __restrict__ p,
+                                                     double* q, double* dy_out, double* r_out) {
+    __shared__ double sh[GNW];
+    double a = 0.0, c = 0.0;
+    for (int l = threadIdx.x; l < m; l += GNT) {
+        a += dy0[l] * p[l];
+        c += dy0[l] * q[l];
+    }
+    const double num = block_sum(a, sh);
+    const double den = block_sum(c, sh);
+    const double beta = (den > 0.0 && isfinite(num / den)) ? num / den : 0.0;
+    for (int l = threadIdx.x; l < m; l += GNT) {
+        const double ql = beta * q[l];
+        q[l] = ql;
+        dy_out[l] = beta * dy0[l];
+        if (r_out) r_out[l] = p[l] - ql;
+    }
+}
+
 __global__ __launch_bounds__(GNT) void k_pcg_init1(PcgBufs b, int warm) {
     extern __shared__ double xs[];   // [2][m]
     __shared__ double sh[GNW];
@@ -253,6 +275,12 @@ __global__ __launch_bounds__(GNT) void k_trigemv(const double* __restrict__ M, i
 int gemv_blocks(int m) {
     int g = (m + GNW - 1) / GNW;
     return g > 1024 ? 1024 : g;
+}
+
+hipError_t launch_warm_scale(int m, const double* dy0, const double* p, double* q, double* dy_out, double* r_out,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_warm_scale, dim3(1), dim3(GNT), 0, st, m, dy0, p, q, dy_out, r_out);
+    return hipGetLastError();
 }
 
 hipError_t launch_pcg_init1(const PcgBufs& b, int warm, hipStream_t st) {

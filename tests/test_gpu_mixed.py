@@ -120,7 +120,12 @@ def test_pcg_mixed_warm_start(ctx):
     assert iw["warm_used"] == 1 and iw["iters"] < ic["iters"]
     f = sla.solve_triangular(L, M @ host(dw) - p, lower=True)
     assert np.linalg.norm(f) <= 1e-10 * 1.001 * np.linalg.norm(sla.solve_triangular(L, p, lower=True))
-    _, ib = P.ipm_pcg_solve(ctx, Am, dev(d2), Linv, dev(p), prm, dy0=dev(-1e3 * xs))
+    ds, is_ = P.ipm_pcg_solve(ctx, Am, dev(d2), Linv, dev(p), prm, dy0=dev(-3.0 * xs))
+    assert is_["warm_used"] == 1 and is_["iters"] == 0 and is_["rounds"] == 0
+    assert np.allclose(host(ds), xs, rtol=1e-8)
+    z = np.random.default_rng(1).standard_normal(xs.size)
+    z -= (z @ M @ xs) / (xs @ M @ xs) * xs
+    _, ib = P.ipm_pcg_solve(ctx, Am, dev(d2), Linv, dev(p), prm, dy0=dev(z))
     assert ib["warm_used"] == 0 and ib["iters"] == ic["iters"]
 
 

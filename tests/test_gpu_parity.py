@@ -178,8 +178,15 @@ def test_pcg_warm_start(ctx):
     assert info_w["warm_used"] == 1 and info_w["iters"] < info_c["iters"]
     ref = oipm.pcg(lambda v: M @ v, L, p, 1e-10, 500, dy0=good)
     assert abs(info_w["iters"] - ref.iters) <= 1
-    bad = -1e3 * xs
-    _, info_b = P.ipm_pcg_solve(ctx, P.Matrix.from_numpy(A), dev(d2), dev(Linv), dev(p), prm, dy0=dev(bad))
+    # a multiple of the solution is scaled back to it (energy-optimal factor): no iteration
+    dy_s, info_s = P.ipm_pcg_solve(ctx, P.Matrix.from_numpy(A), dev(d2), dev(Linv), dev(p), prm,
+                                   dy0=dev(-3.0 * xs))
+    assert info_s["warm_used"] == 1 and info_s["iters"] == 0
+    assert np.allclose(host(dy_s), xs, rtol=1e-8)
+    # a direction M-orthogonal to the solution gets beta = 0 and is rejected
+    z = np.random.default_rng(1).standard_normal(xs.size)
+    z -= (z @ M @ xs) / (xs @ M @ xs) * xs
+    _, info_b = P.ipm_pcg_solve(ctx, P.Matrix.from_numpy(A), dev(d2), dev(Linv), dev(p), prm, dy0=dev(z))
     assert info_b["warm_used"] == 0 and abs(info_b["iters"] - info_c["iters"]) <= 1
 
 

@@ -257,6 +257,49 @@ def test_pcg_energy_error_matches_tolerance():
     assert en <= 10 * tol * np.linalg.norm(fp) / np.sqrt(ev.min())
 
 
+def test_pcg_warm_start_multiple_of_solution_needs_no_iteration():
+    """Any nonzero multiple of the exact solution, negative ones included, is scaled back to
+    the solution by the energy-optimal factor: CG stops before its first iteration."""
+    lp = lpgen.tiny_lp(15, 400, 11)
+    rng = np.random.default_rng(5)
+    d2 = np.exp(rng.uniform(-3, 3, lp.n))
+    M, L, _ = _sketched(lp, d2, 60, 2, 1)
+    p = rng.standard_normal(lp.m)
+    xs = np.linalg.solve(M, p)
+    for c in (-3.0, 1e-3, 7.5):
+        res = ipm.pcg(lambda v: M @ v, L, p, tol=1e-10, maxit=100, dy0=c * xs)
+        assert res.warm_used and res.iters == 0
+        assert np.allclose(res.dy, xs, rtol=1e-9)
+    # a direction M-orthogonal to the solution carries no information: beta = 0, zero start
+    z = rng.standard_normal(lp.m)
+    z -= (z @ M @ xs) / (xs @ M @ xs) * xs
+    res = ipm.pcg(lambda v: M @ v, L, p, tol=1e-10, maxit=100, dy0=z)
+    cold = ipm.pcg(lambda v: M @ v, L, p, tol=1e-10, maxit=100)
+    assert not res.warm_used and res.iters == cold.iters
+
+
+def test_pcg_warm_start_never_increases_the_energy_error():
+    """The scaled warm start is the best multiple of dy0 in the M-norm, so its error is at most
+    that of dy0 itself and of the zero start (minimisation over a line through 0)."""
+    lp = lpgen.tiny_lp(15, 400, 12)
+    rng = np.random.default_rng(6)
+    d2 = np.exp(rng.uniform(-3, 3, lp.n))
+    M, L, _ = _sketched(lp, d2, 60, 2, 2)
+    p = rng.standard_normal(lp.m)
+    xs = np.linalg.solve(M, p)
+    enorm = lambda e: np.sqrt(e @ M @ e)
+    for t in range(20):
+        dy0 = xs * rng.uniform(0.0, 3.0) + rng.standard_normal(lp.m) * rng.uniform(0, 2) * np.linalg.norm(xs)
+        res = ipm.pcg(lambda v: M @ v, L, p, tol=1e-10, maxit=0, dy0=dy0)
+        e = enorm(res.dy - xs)
+        assert e <= enorm(dy0 - xs) * (1 + 1e-12) and e <= enorm(xs) * (1 + 1e-12)
+        # brute force over a grid of multiples
+        grid = np.linspace(-3, 3, 601)
+        best = min(enorm(g * dy0 - xs) for g in grid)
+        if res.warm_used:
+            assert e <= best * (1 + 1e-9)
+
+
 # ------------------------------------------------------------------ step lengths (Algorithm 3, steps 6-7)
 
 def _constraints(x, s, dx, ds, gamma, mu0, r0n, rn, a):
