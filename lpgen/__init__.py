@@ -28,7 +28,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = ["LP", "dense_lp", "tiny_lp", "config", "bf16_round", "f32_round",
-           "CONFIGS"]
+           "CONFIGS", "mlp_init"]
 
 
 @dataclass
@@ -138,3 +138,16 @@ def config(i, seed: Optional[int] = None) -> LP:
                       name=f"cfg{i}s{sd}")
     lp.meta.update(w=cfg["w"], s=cfg["s"], config=i, seed=sd)
     return lp
+
+
+def mlp_init(n_in: int, n_hidden: int, n_out: int, seed: int = 0, out_scale: float = 0.01) -> np.ndarray:
+    """Initial weights of the warm-start network, flat in the layout W1 [H x I], b1 [H],
+    W2 [H x H], b2 [H], W3 [O x H], b3 [O]: W1, W2 ~ N(0, 2 / fan_in) (He et al., 2015),
+    W3 ~ N(0, out_scale^2 / H), biases 0. Returned as float32-representable float64."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((n_hidden, n_in)) * np.sqrt(2.0 / n_in)
+    W2 = rng.standard_normal((n_hidden, n_hidden)) * np.sqrt(2.0 / n_hidden)
+    W3 = rng.standard_normal((n_out, n_hidden)) * (out_scale / np.sqrt(n_hidden))
+    theta = np.concatenate([W1.ravel(), np.zeros(n_hidden), W2.ravel(), np.zeros(n_hidden),
+                            W3.ravel(), np.zeros(n_out)])
+    return f32_round(theta)

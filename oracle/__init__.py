@@ -23,4 +23,4 @@ for Tall/Wide Linear Programs"):
 Readings of passages the paper leaves open are listed in the repository's
 design notes; each function's docstring names the passage it follows.
 """
-from . import sketch, ipm, vertex  # noqa: F401
+from . import sketch, ipm, vertex, mlp  # noqa: F401
