@@ -109,10 +109,11 @@ typedef struct {
                             outer residual p - A D^2 A^T dy recomputed with FP64 accumulation,
                             stop on ||L^-1 r|| <= tol_pcg ||L^-1 p|| for that true residual     */
     int32_t warm_start;  /* IPM_WARM_NONE | IPM_WARM_PREV (previous iteration's dy) |
-                            IPM_WARM_GIVEN (ipm_step_warm's dy0). The initial iterate is
-                            beta dy0 with beta = dy0^T p / dy0^T M dy0 (the multiple of dy0
-                            closest to the solution in the M-norm), kept only if its
-                            preconditioned residual beats that of dy = 0                      */
+                            IPM_WARM_GIVEN (ipm_step_warm's candidates). The initial iterate
+                            is the combination of the candidate vectors closest to the
+                            solution in the M-norm (M = A D^2 A^T; for one candidate v it is
+                            (v^T p / v^T M v) v), kept only if its preconditioned residual
+                            beats that of dy = 0                                              */
     double inner_tol;    /* relative tolerance of each inner CG solve (mixed form)           */
     int32_t max_refine;  /* refinement rounds (mixed form)                                   */
     int32_t reserved;
@@ -214,16 +215,74 @@ int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const dou
 int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* params,
              ipm_step_info* info);
 
-/* ipm_step with an initial CG iterate dy0 [device, m doubles] (used when params->warm_start is
- * IPM_WARM_GIVEN; e.g. the learned warm start). dy0 is read only. */
+/* ipm_step whose CG solve starts from the M-norm-optimal combination of ncand (1 or 2)
+ * candidate vectors dy0 [device, ncand x m doubles, one vector after the other], used when
+ * params->warm_start is IPM_WARM_GIVEN (the learned warm start passes the previous dy and the
+ * network's output). Two candidates nearly parallel in the M-norm (squared sine of their angle
+ * below 1e-8) are reduced to the first. dy0 is read only. */
 int ipm_step_warm(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* params,
-                  const double* dy0, ipm_step_info* info);
+                  const double* dy0, int32_t ncand, ipm_step_info* info);
 
 /* The accepted dy of the last successful ipm_step on this context [device, m doubles] is copied
  * to out. Returns IPM_ERR_ARG if no step was taken yet or m differs. */
 int ipm_last_dy(ipm_ctx* ctx, int64_t m, double* out);
 
 /* ---- measurement ------------------------------------------------------------------------ */
+
+/* ---- learned warm start (a further form of the method; not in the paper) ----------------
+ *
+ * A three-layer ReLU network (FP32) maps features of IPM iteration k >= 1 to a second
+ * warm-start candidate beside the previous direction dy_prev; ipm_step_warm (warm_start =
+ * IPM_WARM_GIVEN, ncand = 2) starts the CG solve from their M-norm-optimal combination.
+ * Features (m + 18): u = dy_prev / ||dy_prev|| (m), 0.1 log ||dy_prev||, 0.1 [mean, std, min,
+ * max] of l = log(x / s) (= log d^2), 0.1 x 12 quantiles of l at levels i/13 (i = 1..12) read
+ * from a 64-bin histogram on [min l, max l] with linear interpolation in the bin, and k / kmax.
+ * Network: h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3; candidate
+ * ||dy_prev|| y. Training target t = (dy - (u^T dy) u) / ||dy_prev|| (the part of the new
+ * direction dy the previous one misses). Loss of a batch: mean over samples of log(e + 1e-10)
+ * with e = 1 - cos^2(y, t), the squared sine of the angle to the target (only the direction of
+ * a candidate matters; the CG iterations a start saves grow like log(1 / e)). Optimiser: Adam. */
+typedef struct {
+    int32_t n_in;        /* inputs; m + 18 for ipm_mlp_features / ipm_mlp_predict            */
+    int32_t n_hidden;    /* width H                                                          */
+    int32_t n_out;       /* outputs (m)                                                      */
+    int32_t reserved;
+    float* params;       /* [device] ipm_mlp_param_count() floats, flat: W1 [H x n_in]
+                            row-major, b1 [H], W2 [H x H], b2 [H], W3 [n_out x H], b3 [n_out]   */
+} ipm_mlp;
+
+int64_t ipm_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out);
+
+/* Features of iteration k (see above) into feat [device, m + 18 floats]. dy_prev [device, m],
+ * x, s [device, n] with x, s > 0. Stream-ordered, no synchronization. */
+int ipm_mlp_features(ipm_ctx* ctx, int64_t m, int64_t n, const double* dy_prev, const double* x,
+                     const double* s, int64_t k, int64_t kmax, float* feat);
+
+/* Training target of one sample: t = (dy - (u^T dy) u) / ||dy_prev||, u = dy_prev / ||dy_prev||
+ * [device, m floats]; dy, dy_prev [device, m doubles] are the accepted directions of
+ * iterations k and k-1. */
+int ipm_mlp_target(ipm_ctx* ctx, int64_t m, const double* dy_prev, const double* dy, float* t);
+
+/* Y [device, batch x n_out] = network(X [device, batch x n_in]), row-major. */
+int ipm_mlp_forward(ipm_ctx* ctx, const ipm_mlp* net, int32_t batch, const float* X, float* Y);
+
+/* Gradient of the batch loss for inputs X and targets T [device, batch x n_out] into grad
+ * [device, ipm_mlp_param_count floats, same layout as params]. If loss is not NULL the call
+ * synchronizes and writes the loss there (host). A sample whose target or output is zero
+ * contributes log(1 + 1e-10) and no gradient. */
+int ipm_mlp_backward(ipm_ctx* ctx, const ipm_mlp* net, int32_t batch, const float* X, const float* T,
+                     float* grad, double* loss);
+
+/* One Adam step t >= 1 (Kingma and Ba, 2015) on count parameters with moment buffers m1, m2
+ * [device, zero before the first step]: m1 = b1 m1 + (1-b1) g, m2 = b2 m2 + (1-b2) g^2,
+ * p -= lr (m1 / (1-b1^t)) / (sqrt(m2 / (1-b2^t)) + eps). */
+int ipm_mlp_adam(ipm_ctx* ctx, int64_t count, float* params, const float* grad, float* m1, float* m2,
+                 int64_t t, double lr, double beta1, double beta2, double eps);
+
+/* Warm-start candidate of iteration k: features, forward pass, dy0 = ||dy_prev|| y
+ * [device, n_out doubles]. net->n_in must equal net->n_out + 18. */
+int ipm_mlp_predict(ipm_ctx* ctx, const ipm_mlp* net, int64_t n, const double* dy_prev, const double* x,
+                    const double* s, int64_t k, int64_t kmax, double* dy0);
 
 /* q = A diag(d2) A^T v in one pass over A (the CG matvec). v, q [device] m doubles;
  * d2 [device] n doubles. */

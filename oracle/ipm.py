@@ -161,12 +161,15 @@ def pcg(matvec: Callable, L: np.ndarray, p: np.ndarray, tol: float, maxit: int,
     ``matvec(v)`` applies M = A D^2 A^T. The residual norm reported is the
     paper's ||f|| = ||Q^{-1/2}(M dy - p)|| = ||L^{-1} r|| (Section 3.1).
 
-    Warm start (not in the paper): dy0 is first scaled by the factor
-    beta = dy0^T p / dy0^T M dy0 that minimises the M-norm error
-    ||dy* - beta dy0||_M (a one-dimensional Galerkin projection; beta = 0 if
-    dy0^T M dy0 <= 0). The scaled iterate is kept only if its preconditioned
-    residual is smaller than that of 0, so the stop test, relative to
-    ||L^{-1} p||, is unchanged.
+    Warm start (not in the paper): dy0 holds one candidate vector (shape (m,))
+    or two (shape (m, 2)). The initial iterate is their combination V c
+    closest to the solution in the M-norm, c solving the Galerkin system
+    (V^T M V) c = V^T p. Two candidates whose Gram determinant is at most
+    1e-8 a11 a22 (nearly parallel in the M-norm) or with a non-positive
+    M-norm are reduced to one: beta = v^T p / v^T M v for the first with a
+    positive M-norm (beta = 0 if none). The iterate is kept only if its
+    preconditioned residual is smaller than that of 0, so the stop test,
+    relative to ||L^{-1} p||, is unchanged.
     """
     def lsolve(r):
         return sla.solve_triangular(L, r, lower=True)
@@ -182,13 +185,23 @@ def pcg(matvec: Callable, L: np.ndarray, p: np.ndarray, tol: float, maxit: int,
     wv = wp
     warm_used = False
     if dy0 is not None:
-        q0 = matvec(dy0)
-        den = float(dy0 @ q0)
-        beta = float(dy0 @ p) / den if den > 0.0 else 0.0
-        r0 = p - beta * q0
+        V = dy0.reshape(m, -1)
+        Q = np.stack([matvec(V[:, i]) for i in range(V.shape[1])], axis=1)
+        G = V.T @ Q
+        rhs = V.T @ p
+        coef = np.zeros(V.shape[1])
+        if V.shape[1] == 2 and G[0, 0] > 0 and G[1, 1] > 0 and \
+                G[0, 0] * G[1, 1] - G[0, 1] * G[1, 0] > 1e-8 * G[0, 0] * G[1, 1]:
+            coef = np.linalg.solve(G, rhs)
+        else:
+            for i in range(V.shape[1]):
+                if G[i, i] > 0:
+                    coef[i] = rhs[i] / G[i, i]
+                    break
+        r0 = p - Q @ coef
         w0 = lsolve(r0)
         if float(w0 @ w0) < rho_star:
-            dy, r, wv, warm_used = beta * dy0, r0, w0, True
+            dy, r, wv, warm_used = V @ coef, r0, w0, True
     rho = float(wv @ wv)
     hist = [np.sqrt(rho)]
     thresh = tol * np.sqrt(rho_star)

@@ -255,17 +255,20 @@ def ipm_step(ctx: Context, prob: Problem, st: State, params: Params) -> dict:
 
 
 def ipm_step_warm(ctx: Context, prob: Problem, st: State, params: Params, dy0) -> dict:
-    """ipm_step with the initial CG iterate dy0 (device FP64, m); params.warm_start must be
-    IPM_WARM_GIVEN for dy0 to be used."""
+    """ipm_step whose CG solve starts from the M-norm-optimal combination of the candidate
+    vectors dy0 (device FP64, shape (m,) or (ncand, m) with ncand 1 or 2); params.warm_start
+    must be IPM_WARM_GIVEN for them to be used."""
     torch = _torch()
     _need_dev(dy0, "dy0", torch.float64)
     return _step(ctx, prob, st, params, dy0)
 
 
-def ipm_last_dy(ctx: Context, m: int, device: int = 0):
-    """The dy accepted by the last successful step on ctx."""
+def ipm_last_dy(ctx: Context, m: int, device: int = 0, out=None):
+    """The dy accepted by the last successful step on ctx (into ``out`` if given)."""
     torch = _torch()
-    out = torch.empty(m, dtype=torch.float64, device=f"cuda:{device}")
+    if out is None:
+        out = torch.empty(m, dtype=torch.float64, device=f"cuda:{device}")
+    _need_dev(out, "out", torch.float64)
     ctx.check(ctx.lib.ipm_last_dy(ctx.h, m, _ptr(out)))
     return out
 
@@ -278,8 +281,9 @@ def _step(ctx: Context, prob: Problem, st: State, params: Params, dy0) -> dict:
     if dy0 is None:
         rc = ctx.lib.ipm_step(ctx.h, ctypes.byref(pc), ctypes.byref(sc), ctypes.byref(prm), ctypes.byref(info))
     else:
+        ncand = 1 if dy0.dim() == 1 else dy0.shape[0]
         rc = ctx.lib.ipm_step_warm(ctx.h, ctypes.byref(pc), ctypes.byref(sc), ctypes.byref(prm), _ptr(dy0),
-                                   ctypes.byref(info))
+                                   ncand, ctypes.byref(info))
     st.k, st.mu0, st.r0norm = sc.k, sc.mu0, sc.r0norm
     d = info.as_dict()
     d["rc"] = rc
@@ -298,12 +302,32 @@ class SolveResult:
 
 
 def solve(ctx: Context, prob: Problem, params: Params, maxit: int = 200, st: Optional[State] = None,
-          callback=None) -> SolveResult:
-    """Algorithm 3 from x = s = 1, y = 0 until the stop test holds or maxit iterations."""
-    st = st or State.initial(prob.A.m, prob.A.n, prob.b.device.index or 0)
+          callback=None, net=None, kmax: int = 200) -> SolveResult:
+    """Algorithm 3 from x = s = 1, y = 0 until the stop test holds or maxit iterations.
+
+    With a warm-start network ``net`` (learned.Mlp), every iteration after the first starts its
+    CG solve from the M-norm-optimal combination of the previous direction and the network's
+    prediction (ipm_mlp_predict, then ipm_step_warm with both as candidates)."""
+    from dataclasses import replace
+    dev = prob.b.device.index or 0
+    st = st or State.initial(prob.A.m, prob.A.n, dev)
     infos = []
+    prm_warm = replace(params, warm_start=IPM_WARM_GIVEN) if net is not None else None
+    cand = None
+    if net is not None:
+        from .learned import mlp_predict_into
+        torch = _torch()
+        cand = torch.empty((2, prob.A.m), dtype=torch.float64, device=f"cuda:{dev}")   # [previous dy; network]
+    have_prev = False
     for _ in range(maxit + 1):
-        info = ipm_step(ctx, prob, st, params)
+        if net is not None and have_prev:
+            mlp_predict_into(ctx, net, cand[0], st.x, st.s, st.k, kmax, cand[1])
+            info = ipm_step_warm(ctx, prob, st, prm_warm, cand)
+        else:
+            info = ipm_step(ctx, prob, st, params)
+        if net is not None and info["rc"] != IPM_CONVERGED:
+            ipm_last_dy(ctx, prob.A.m, dev, out=cand[0])
+            have_prev = True
         infos.append(info)
         if callback is not None:
             callback(st, info)

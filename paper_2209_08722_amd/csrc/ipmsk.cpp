@@ -22,7 +22,7 @@ namespace {
 enum WsId {
     W_PART = 0, W_COLPART, W_RED, W_D2, W_RD, W_DS, W_DX, W_RP, W_P, W_DY, W_RHAT, W_G1, W_G2, W_U, W_B,
     W_L, W_X, W_XT, W_T, W_SCAL, W_PCG_VEC, W_PCG_RHO, W_PCG_CD, W_PCG_CI, W_STATUS, W_PART3, W_PARTMIN,
-    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_COUNT
+    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_MLPF, W_MLPD, W_MLPI, W_WQ, W_COUNT
 };
 
 struct TimedPair {
@@ -330,9 +330,29 @@ struct PcgCfg {
     int* last_iters;    // first batch size hint, updated with the count of this solve
 };
 
-// CG with preconditioner X^T X (X = L^{-1}); dy_out receives the solution.
+// Initial iterate from ncand (1 or 2) candidate vectors cand[0:m], cand[m:2m]: their
+// M-norm-optimal combination into dy_out, M dy_out into q_out and, if r_out is given,
+// p - M dy_out into r_out. The matvecs accumulate in FP64 when acc64 is set.
+int warm_combination(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const StripPlan& pl, const double* p,
+                     const double* cand, int ncand, int acc64, double* dy_out, double* q_out, double* r_out) {
+    const int m = (int)A->m;
+    double* q2 = nullptr;
+    CHK(matvec_pass(ctx, A, d2, cand, q_out, pl, nullptr, -1, acc64));
+    if (ncand > 1) {
+        CHK(ws(ctx, W_WQ, (size_t)m, &q2));
+        CHK(matvec_pass(ctx, A, d2, cand + m, q2, pl, nullptr, -1, acc64));
+    }
+    HIPCHK(launch_warm_galerkin(m, ncand, cand, ncand > 1 ? cand + m : nullptr, p, q_out, q2, dy_out, q_out, r_out,
+                                ctx->stream));
+    return IPM_OK;
+}
+
+// CG with preconditioner X^T X (X = L^{-1}); dy_out receives the solution. With ncand > 0 the
+// solve starts from the combination of the candidate vectors (kept only if its preconditioned
+// residual is below that of the zero start); cand may alias dy_out when ncand is 1.
 int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X, const double* p, double* dy_out,
-           int warm, const ipm_params* prm, const PcgCfg& cfg, PcgOut* out) {
+           const double* cand, int ncand, const ipm_params* prm, const PcgCfg& cfg, PcgOut* out) {
+    const int warm = ncand > 0 ? 1 : 0;
     hipStream_t st = ctx->stream;
     const int m = (int)A->m;
     double* XT = nullptr;
@@ -370,10 +390,7 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     b.stag_window = prm->stag_window;
     b.maxit = cfg.maxit;
     HIPCHK(launch_fill_i32(ci, PI_COUNT, 0, st));
-    if (warm) {
-        CHK(matvec_pass(ctx, A, d2, dy_out, b.q, pl, nullptr, -1, cfg.acc64));
-        HIPCHK(launch_warm_scale(m, dy_out, p, b.q, dy_out, nullptr, st));
-    }
+    if (warm) CHK(warm_combination(ctx, A, d2, pl, p, cand, ncand, cfg.acc64, dy_out, b.q, nullptr));
     HIPCHK(launch_pcg_init1(b, warm, st));
     HIPCHK(launch_pcg_init2(b, warm, dy_out, st));
     int* hi = reinterpret_cast<int*>(ctx->pinned);
@@ -424,7 +441,7 @@ int precond_norm2(ipm_ctx* ctx, const double* X, int m, const double* v, double*
 // that does not shrink the residual by half (FP32 accumulation error comparable to the
 // preconditioned system's scale, late in the IPM) switches the inner solves to FP64 accumulation.
 int do_pcg_mixed(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X, const double* p,
-                 double* dy, const double* dy0, const ipm_params* prm, PcgOut* out) {
+                 double* dy, const double* cand, int ncand, const ipm_params* prm, PcgOut* out) {
     hipStream_t st = ctx->stream;
     const int m = (int)A->m;
     const StripPlan pl = strip_plan(A->dtype, m, A->n, ctx->num_cu, STRIP_MATVEC);
@@ -441,10 +458,9 @@ int do_pcg_mixed(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const doub
     HIPCHK(launch_transpose(X, XT, m, st));
     CHK(precond_norm2(ctx, X, m, p, g, sc));
     out->warm_used = 0;
-    if (dy0) {
-        // energy-optimal multiple of dy0 and its residual, both with FP64 accumulation
-        CHK(matvec_pass(ctx, A, d2, dy0, delta, pl, nullptr, -1, 1));
-        HIPCHK(launch_warm_scale(m, dy0, p, delta, dyw, r, st));
+    if (ncand > 0) {
+        // M-norm-optimal combination of the candidates and its residual, FP64 accumulation
+        CHK(warm_combination(ctx, A, d2, pl, p, cand, ncand, 1, dyw, delta, r));
         CHK(precond_norm2(ctx, X, m, r, g, sc + 2));
         HIPCHK(hipMemcpyAsync(hd, sc, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -491,7 +507,7 @@ int do_pcg_mixed(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const doub
         cfg.xt_ready = true;
         cfg.last_iters = fp64_inner ? &ctx->last_pcg_iters : &ctx->last_inner_iters;
         PcgOut io{};
-        CHK(do_pcg(ctx, A, d2, X, r, delta, 0, prm, cfg, &io));
+        CHK(do_pcg(ctx, A, d2, X, r, delta, nullptr, 0, prm, cfg, &io));
         total += io.iters;
         ++rounds;
         if (io.status == IPM_ERR_BREAKDOWN) {
@@ -685,10 +701,10 @@ int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const dou
             HIPCHK(hipMemcpyAsync(w0, dy, sizeof(double) * m, hipMemcpyDeviceToDevice, ctx->stream));
             dy0 = w0;
         }
-        CHK(do_pcg_mixed(ctx, A, d2, Linv, p, dy, dy0, params, &o));
+        CHK(do_pcg_mixed(ctx, A, d2, Linv, p, dy, dy0, dy0 ? 1 : 0, params, &o));
     } else {
         PcgCfg cfg{params->tol_pcg, params->maxit_pcg, 1, false, &ctx->last_pcg_iters};
-        CHK(do_pcg(ctx, A, d2, Linv, p, dy, warm ? 1 : 0, params, cfg, &o));
+        CHK(do_pcg(ctx, A, d2, Linv, p, dy, warm ? dy : nullptr, warm ? 1 : 0, params, cfg, &o));
     }
     if (info) {
         info->iters = o.iters;
@@ -719,7 +735,7 @@ int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const
 namespace {
 
 int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* prm, const double* dy_given,
-              ipm_step_info* info) {
+              int n_given, ipm_step_info* info) {
     if (!ctx) return IPM_ERR_ARG;
     if (!prob || !state || !info) return fail(ctx, IPM_ERR_ARG, "null pointer");
     std::memset(info, 0, sizeof(*info));
@@ -807,10 +823,13 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
 
     // initial CG iterate: the previous accepted dy or the caller's, the same for every draw
     const double* dy0 = nullptr;
+    int ncand = 0;
     if (prm->warm_start == IPM_WARM_GIVEN) {
         dy0 = dy_given;
+        ncand = n_given;
     } else if (prm->warm_start == IPM_WARM_PREV && ctx->prev_m == m) {
         dy0 = reinterpret_cast<const double*>(ctx->ws[W_PREV]);
+        ncand = 1;
     }
 
     // Algorithm 1 with redraws of W: sketch, factor, CG. The mixed form keeps B in FP32.
@@ -850,11 +869,10 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
             continue;
         }
         if (mixed) {
-            CHK(do_pcg_mixed(ctx, A, d2, X, p, dyv, dy0, prm, &po));
+            CHK(do_pcg_mixed(ctx, A, d2, X, p, dyv, dy0, ncand, prm, &po));
         } else {
-            if (dy0) HIPCHK(hipMemcpyAsync(dyv, dy0, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
             PcgCfg cfg{prm->tol_pcg, prm->maxit_pcg, 1, false, &ctx->last_pcg_iters};
-            CHK(do_pcg(ctx, A, d2, X, p, dyv, dy0 ? 1 : 0, prm, cfg, &po));
+            CHK(do_pcg(ctx, A, d2, X, p, dyv, dy0, ncand, prm, cfg, &po));
         }
         if (po.status == IPM_ERR_BREAKDOWN) {
             info->status = IPM_ERR_BREAKDOWN;
@@ -932,14 +950,154 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
 extern "C" {
 
 int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* prm, ipm_step_info* info) {
-    return step_impl(ctx, prob, state, prm, nullptr, info);
+    return step_impl(ctx, prob, state, prm, nullptr, 0, info);
 }
 
 int ipm_step_warm(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* prm, const double* dy0,
-                  ipm_step_info* info) {
+                  int32_t ncand, ipm_step_info* info) {
     if (!ctx) return IPM_ERR_ARG;
     if (!dy0) return fail(ctx, IPM_ERR_ARG, "dy0 is null");
-    return step_impl(ctx, prob, state, prm, dy0, info);
+    if (ncand < 1 || ncand > 2) return fail(ctx, IPM_ERR_ARG, "ncand must be 1 or 2");
+    return step_impl(ctx, prob, state, prm, dy0, ncand, info);
+}
+
+}  // extern "C"
+
+// ---- learned warm start ----
+
+namespace {
+
+int check_net(ipm_ctx* ctx, const ipm_mlp* net) {
+    if (!net || !net->params) return fail(ctx, IPM_ERR_ARG, "network or its parameters are null");
+    if (net->n_out < 1 || net->n_hidden < 1 || net->n_in < 1 || net->n_in > (1 << 20) ||
+        net->n_hidden > 8192 || net->n_out > (1 << 20))
+        return fail(ctx, IPM_ERR_ARG, "bad network shape (%d, %d, %d)", net->n_in, net->n_hidden, net->n_out);
+    return IPM_OK;
+}
+
+struct MlpWs {
+    float *act1, *act2, *Y, *dY, *dZ2, *dZ1, *feat;
+    double *ratio, *loss, *nrm, *work;
+    int* hist;
+};
+
+int mlp_ws(ipm_ctx* ctx, const ipm_mlp* net, int B, int64_t n, MlpWs* w) {
+    const int64_t H = net->n_hidden, O = net->n_out, I = net->n_in;
+    float* f = nullptr;
+    CHK(ws(ctx, W_MLPF, (size_t)B * (4 * H + 2 * O) + (size_t)I + 64, &f));
+    w->act1 = f;
+    w->act2 = w->act1 + B * H;
+    w->dZ2 = w->act2 + B * H;
+    w->dZ1 = w->dZ2 + B * H;
+    w->Y = w->dZ1 + B * H;
+    w->dY = w->Y + B * O;
+    w->feat = w->dY + B * O;
+    double* d = nullptr;
+    const int fb = n > 0 ? feat_blocks(n) : 1;
+    CHK(ws(ctx, W_MLPD, (size_t)B + 8 + 4 * (size_t)fb + 4, &d));
+    w->ratio = d;
+    w->loss = d + B;
+    w->nrm = d + B + 1;
+    w->work = d + B + 8;
+    CHK(ws(ctx, W_MLPI, 64, &w->hist));
+    return IPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t ipm_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out) {
+    if (n_in < 1 || n_hidden < 1 || n_out < 1) return -1;
+    return mlp_param_count(n_in, n_hidden, n_out);
+}
+
+int ipm_mlp_features(ipm_ctx* ctx, int64_t m, int64_t n, const double* dy_prev, const double* x, const double* s,
+                     int64_t k, int64_t kmax, float* feat) {
+    if (!ctx) return IPM_ERR_ARG;
+    if (!dy_prev || !x || !s || !feat) return fail(ctx, IPM_ERR_ARG, "null pointer");
+    if (m < 1 || m > (1 << 20) || n < 1 || kmax < 1 || k < 0) return fail(ctx, IPM_ERR_ARG, "bad sizes");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    ipm_mlp shape{(int32_t)m + 18, 1, (int32_t)m, 0, nullptr};
+    MlpWs w{};
+    CHK(mlp_ws(ctx, &shape, 1, n, &w));
+    HIPCHK(launch_mlp_features((int)m, n, dy_prev, x, s, (double)k / (double)kmax, w.work, w.hist, feat, nullptr,
+                               ctx->stream));
+    return IPM_OK;
+}
+
+int ipm_mlp_target(ipm_ctx* ctx, int64_t m, const double* dy_prev, const double* dy, float* t) {
+    if (!ctx) return IPM_ERR_ARG;
+    if (!dy_prev || !dy || !t || m < 1 || m > (1 << 20)) return fail(ctx, IPM_ERR_ARG, "bad arguments");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    HIPCHK(launch_mlp_target((int)m, dy_prev, dy, t, ctx->stream));
+    return IPM_OK;
+}
+
+int ipm_mlp_forward(ipm_ctx* ctx, const ipm_mlp* net, int32_t batch, const float* X, float* Y) {
+    if (!ctx) return IPM_ERR_ARG;
+    CHK(check_net(ctx, net));
+    if (batch < 1 || batch > 65536 || !X || !Y) return fail(ctx, IPM_ERR_ARG, "bad batch or null pointer");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    MlpWs w{};
+    CHK(mlp_ws(ctx, net, batch, 0, &w));
+    HIPCHK(launch_mlp_forward(net->n_in, net->n_hidden, net->n_out, net->params, batch, X, w.act1, w.act2, Y,
+                              ctx->stream));
+    return IPM_OK;
+}
+
+int ipm_mlp_backward(ipm_ctx* ctx, const ipm_mlp* net, int32_t batch, const float* X, const float* T, float* grad,
+                     double* loss) {
+    if (!ctx) return IPM_ERR_ARG;
+    CHK(check_net(ctx, net));
+    if (batch < 1 || batch > 65536 || !X || !T || !grad) return fail(ctx, IPM_ERR_ARG, "bad batch or null pointer");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    MlpWs w{};
+    CHK(mlp_ws(ctx, net, batch, 0, &w));
+    const int I = net->n_in, H = net->n_hidden, O = net->n_out;
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_mlp_forward(I, H, O, net->params, batch, X, w.act1, w.act2, w.Y, st));
+    HIPCHK(launch_mlp_backward(I, H, O, net->params, batch, X, T, w.act1, w.act2, w.Y, w.dY, w.dZ2, w.dZ1, w.ratio,
+                               grad, w.loss, st));
+    if (loss) {
+        double* hd = reinterpret_cast<double*>(ctx->pinned) + 128;
+        HIPCHK(hipMemcpyAsync(hd, w.loss, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        *loss = hd[0];
+    }
+    return IPM_OK;
+}
+
+int ipm_mlp_adam(ipm_ctx* ctx, int64_t count, float* params, const float* grad, float* m1, float* m2, int64_t t,
+                 double lr, double beta1, double beta2, double eps) {
+    if (!ctx) return IPM_ERR_ARG;
+    if (count < 1 || !params || !grad || !m1 || !m2 || t < 1) return fail(ctx, IPM_ERR_ARG, "bad Adam arguments");
+    if (!(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0 && lr >= 0))
+        return fail(ctx, IPM_ERR_ARG, "bad Adam hyperparameters");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    const double c1 = 1.0 / (1.0 - std::pow(beta1, (double)t));
+    const double c2 = 1.0 / (1.0 - std::pow(beta2, (double)t));
+    HIPCHK(launch_mlp_adam(count, params, grad, m1, m2, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)c1,
+                           (float)c2, ctx->stream));
+    return IPM_OK;
+}
+
+int ipm_mlp_predict(ipm_ctx* ctx, const ipm_mlp* net, int64_t n, const double* dy_prev, const double* x,
+                    const double* s, int64_t k, int64_t kmax, double* dy0) {
+    if (!ctx) return IPM_ERR_ARG;
+    CHK(check_net(ctx, net));
+    if (net->n_in != net->n_out + 18) return fail(ctx, IPM_ERR_ARG, "n_in must be n_out + 18");
+    if (!dy_prev || !x || !s || !dy0) return fail(ctx, IPM_ERR_ARG, "null pointer");
+    if (n < 1 || kmax < 1 || k < 0) return fail(ctx, IPM_ERR_ARG, "bad sizes");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    MlpWs w{};
+    CHK(mlp_ws(ctx, net, 1, n, &w));
+    const int m = net->n_out;
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_mlp_features(m, n, dy_prev, x, s, (double)k / (double)kmax, w.work, w.hist, w.feat, w.nrm, st));
+    HIPCHK(launch_mlp_forward(net->n_in, net->n_hidden, m, net->params, 1, w.feat, w.act1, w.act2, w.Y, st));
+    HIPCHK(launch_mlp_scale_out(m, w.Y, w.nrm, dy0, st));
+    return IPM_OK;
 }
 
 int ipm_last_dy(ipm_ctx* ctx, int64_t m, double* out) {

@@ -123,8 +123,8 @@ hipError_t launch_pcg_init2(const PcgBufs& b, int warm, const double* dy_in, hip
 hipError_t launch_pcg_gemv1(const PcgBufs& b, int j, hipStream_t st);
 hipError_t launch_pcg_gemv2(const PcgBufs& b, int j, hipStream_t st);
 hipError_t launch_pcg_finish(const PcgBufs& b, double* dy_out, double* info_out, hipStream_t st);
-hipError_t launch_warm_scale(int m, const double* dy0, const double* p, double* q, double* dy_out, double* r_out,
-                             hipStream_t st);
+hipError_t launch_warm_galerkin(int m, int nc, const double* v1, const double* v2, const double* p, const double* q1,
+                                const double* q2, double* dy_out, double* q_out, double* r_out, hipStream_t st);
 // y = L^{-1} x (lower) or (L^{-1})^T x (upper, given XT) - plain triangular GEMV.
 hipError_t launch_trigemv(const double* M, int m, int lower, const double* xin, double* yout, hipStream_t st);
 
@@ -145,5 +145,20 @@ hipError_t launch_update(int64_t n, int m, double* x, double* y, double* s, cons
 // y += alpha * x (m-vectors); out[0] = x^T y (one block).
 hipError_t launch_axpy(int m, double alpha, const double* x, double* y, hipStream_t st);
 hipError_t launch_dot(int m, const double* x, const double* y, double* out, hipStream_t st);
+
+// ---- learned warm start (mlp.hip) ----
+int64_t mlp_param_count(int I, int H, int O);
+int feat_blocks(int64_t n);   // work needs 4 * feat_blocks(n) + 4 doubles
+hipError_t launch_mlp_features(int m, int64_t n, const double* dy_prev, const double* x, const double* s,
+                               double kfrac, double* work, int* hist, float* feat, double* nrm_out, hipStream_t st);
+hipError_t launch_mlp_forward(int I, int H, int O, const float* theta, int B, const float* X, float* act1,
+                              float* act2, float* Y, hipStream_t st);
+hipError_t launch_mlp_backward(int I, int H, int O, const float* theta, int B, const float* X, const float* T,
+                               const float* act1, const float* act2, const float* Y, float* dY, float* dZ2,
+                               float* dZ1, double* ratio, float* grad, double* loss, hipStream_t st);
+hipError_t launch_mlp_adam(int64_t count, float* p, const float* g, float* m1, float* m2, float lr, float b1, float b2,
+                           float eps, float c1, float c2, hipStream_t st);
+hipError_t launch_mlp_scale_out(int m, const float* y, const double* nrm, double* dy0, hipStream_t st);
+hipError_t launch_mlp_target(int m, const double* dy_prev, const double* dy, float* t, hipStream_t st);
 
 }  // namespace ipmsk

@@ -86,24 +86,46 @@ __device__ __forceinline__ double finish_upper(const double* __restrict__ M, int
     return wave_sum(acc);
 }
 
-// Warm start scaling: beta = dy0^T p / dy0^T q with q = M dy0 minimises ||dy* - beta dy0||_M
-// (beta = 0 when dy0^T q <= 0). Scales q in place, writes beta dy0 (dy_out may alias dy0) and,
-// if r_out is given, r_out = p - beta q. One block: the vectors have m entries.
-__global__ __launch_bounds__(GNT) void k_warm_scale(int m, const double* dy0, const double* __restrict__ p,
-                                                     double* q, double* dy_out, double* r_out) {
+// Warm start from up to two candidate vectors v1, v2 with q_i = M v_i: the combination
+// alpha v1 + beta v2 closest to the solution in the M-norm (Galerkin condition on the span:
+// [v1'q1 v1'q2; v1'q2 v2'q2] [alpha; beta] = [v1'p; v2'p]). When the candidates are nearly
+// parallel in the M-norm (det <= 1e-8 a11 a22) or one of them has a non-positive M-norm, the
+// single-vector rule alpha = v1'p / v1'q1 (or the same for v2) is used. Writes
+// dy_out = alpha v1 + beta v2 (may alias v1), q_out = alpha q1 + beta q2 (may alias q1) and, if
+// r_out is given, r_out = p - q_out. One block: the vectors have m entries.
+__global__ __launch_bounds__(GNT) void k_warm_galerkin(int m, int nc, const double* v1, const double* v2,
+                                                        const double* __restrict__ p, const double* q1,
+                                                        const double* q2, double* dy_out, double* q_out,
+                                                        double* r_out) {
     __shared__ double sh[GNW];
-    double a = 0.0, c = 0.0;
+    double s11 = 0.0, s12 = 0.0, s22 = 0.0, s1p = 0.0, s2p = 0.0;
     for (int l = threadIdx.x; l < m; l += GNT) {
-        a += dy0[l] * p[l];
-        c += dy0[l] * q[l];
+        s11 += v1[l] * q1[l];
+        s1p += v1[l] * p[l];
+        if (nc > 1) {
+            s12 += v1[l] * q2[l];
+            s22 += v2[l] * q2[l];
+            s2p += v2[l] * p[l];
+        }
     }
-    const double num = block_sum(a, sh);
-    const double den = block_sum(c, sh);
-    const double beta = (den > 0.0 && isfinite(num / den)) ? num / den : 0.0;
+    const double a11 = block_sum(s11, sh), b1 = block_sum(s1p, sh);
+    const double a12 = block_sum(s12, sh), a22 = block_sum(s22, sh), b2 = block_sum(s2p, sh);
+    double alpha = 0.0, beta = 0.0;
+    const double det = a11 * a22 - a12 * a12;
+    if (nc > 1 && a11 > 0.0 && a22 > 0.0 && det > 1e-8 * a11 * a22) {
+        alpha = (b1 * a22 - b2 * a12) / det;
+        beta = (a11 * b2 - a12 * b1) / det;
+    } else if (a11 > 0.0) {
+        alpha = b1 / a11;
+    } else if (nc > 1 && a22 > 0.0) {
+        beta = b2 / a22;
+    }
+    if (!isfinite(alpha) || !isfinite(beta)) alpha = beta = 0.0;
     for (int l = threadIdx.x; l < m; l += GNT) {
-        const double ql = beta * q[l];
-        q[l] = ql;
-        dy_out[l] = beta * dy0[l];
+        const double ql = nc > 1 ? alpha * q1[l] + beta * q2[l] : alpha * q1[l];
+        const double dl = nc > 1 ? alpha * v1[l] + beta * v2[l] : alpha * v1[l];
+        q_out[l] = ql;
+        dy_out[l] = dl;
         if (r_out) r_out[l] = p[l] - ql;
     }
 }
@@ -277,9 +299,9 @@ int gemv_blocks(int m) {
     return g > 1024 ? 1024 : g;
 }
 
-hipError_t launch_warm_scale(int m, const double* dy0, const double* p, double* q, double* dy_out, double* r_out,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(k_warm_scale, dim3(1), dim3(GNT), 0, st, m, dy0, p, q, dy_out, r_out);
+hipError_t launch_warm_galerkin(int m, int nc, const double* v1, const double* v2, const double* p, const double* q1,
+                                const double* q2, double* dy_out, double* q_out, double* r_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_warm_galerkin, dim3(1), dim3(GNT), 0, st, m, nc, v1, v2, p, q1, q2, dy_out, q_out, r_out);
     return hipGetLastError();
 }
 

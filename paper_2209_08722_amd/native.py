@@ -78,6 +78,11 @@ class IpmStepInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class IpmMlp(ctypes.Structure):
+    _fields_ = [("n_in", c_int32), ("n_hidden", c_int32), ("n_out", c_int32), ("reserved", c_int32),
+                ("params", c_void_p)]
+
+
 # (name, restype, argtypes) of every exported function
 SIGNATURES = [
     ("ipm_ctx_create", c_int, [POINTER(c_void_p), c_int, c_void_p]),
@@ -94,9 +99,20 @@ SIGNATURES = [
     ("ipm_step", c_int, [c_void_p, POINTER(IpmProblem), POINTER(IpmState), POINTER(IpmParams),
                          POINTER(IpmStepInfo)]),
     ("ipm_step_warm", c_int, [c_void_p, POINTER(IpmProblem), POINTER(IpmState), POINTER(IpmParams), c_void_p,
-                              POINTER(IpmStepInfo)]),
+                              c_int32, POINTER(IpmStepInfo)]),
     ("ipm_last_dy", c_int, [c_void_p, c_int64, c_void_p]),
     ("ipm_normal_matvec", c_int, [c_void_p, POINTER(IpmMatrix), c_void_p, c_void_p, c_void_p]),
+    ("ipm_mlp_param_count", c_int64, [c_int32, c_int32, c_int32]),
+    ("ipm_mlp_features", c_int, [c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_int64,
+                                 c_void_p]),
+    ("ipm_mlp_target", c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    ("ipm_mlp_forward", c_int, [c_void_p, POINTER(IpmMlp), c_int32, c_void_p, c_void_p]),
+    ("ipm_mlp_backward", c_int, [c_void_p, POINTER(IpmMlp), c_int32, c_void_p, c_void_p, c_void_p,
+                                 POINTER(c_double)]),
+    ("ipm_mlp_adam", c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_double,
+                             c_double, c_double, c_double]),
+    ("ipm_mlp_predict", c_int, [c_void_p, POINTER(IpmMlp), c_int64, c_void_p, c_void_p, c_void_p, c_int64,
+                                c_int64, c_void_p]),
     ("ipm_ctx_set_timing", c_int, [c_void_p, c_int32]),
     ("ipm_kernel_time", c_int, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]),
 ]

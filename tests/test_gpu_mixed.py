@@ -237,6 +237,34 @@ def test_step_warm_given_matches_oracle(ctx):
     assert ginfo["dy_norm"] == pytest.approx(np.linalg.norm(dy), rel=1e-12)
 
 
+@pytest.mark.parametrize("precision", ["plain", "mixed"])
+def test_step_two_candidates_matches_oracle(ctx, precision):
+    """Two candidates whose span holds the Newton solution: both sides start from it (no CG
+    iteration) and take the same step."""
+    lp = lpgen.dense_lp(40, 1500, seed=10, storage="f64" if precision == "plain" else "bf16")
+    prob = P.Problem.from_lp(lp, dtype=tdtype(lp.storage))
+    oprm = oipm.Params(w=160, s=2, seed=4)
+    gprm = P.Params(w=160, s=2, seed=4, warm_start=P.IPM_WARM_GIVEN,
+                    precision=P.IPM_MIXED if precision == "mixed" else P.IPM_PLAIN)
+    st = oipm.initial_state(lp.A, lp.b, lp.c)
+    for _ in range(4):
+        st, _ = oipm.step(lp.A, lp.b, lp.c, st, oprm, "sketch")
+    d2 = st.x / st.s
+    _, rd = oipm.residuals(lp.A, lp.b, lp.c, st.x, st.y, st.s)
+    p = oipm.rhs_p(lp.A, lp.b, st.x, st.s, rd, oprm.sigma, float(st.x @ st.s) / lp.n)
+    xs = np.linalg.solve((lp.A * d2) @ lp.A.T, p)
+    v1 = np.random.default_rng(2).standard_normal(lp.m)
+    cands = np.stack([v1, 2.5 * xs - 0.7 * v1])
+    gst = P.State(dev(st.x), dev(st.y), dev(st.s), st.k, st.mu0, st.r0norm)
+    ginfo = P.ipm_step_warm(ctx, prob, gst, gprm, dev(cands))
+    new, oinfo = oipm.step(lp.A, lp.b, lp.c, st, oprm, "sketch", dy0=cands.T.copy(), keep=True)
+    assert ginfo["warm_used"] == 1 and oinfo.extra["pcg"].warm_used
+    assert ginfo["pcg_iters"] == 0 and oinfo.pcg_iters == 0
+    for name in ("x", "y", "s"):
+        g, o = host(getattr(gst, name)), getattr(new, name)
+        assert np.linalg.norm(g - o) <= 1e-9 * np.linalg.norm(o)
+
+
 def test_warm_given_needs_dy0(ctx):
     lp = lpgen.dense_lp(10, 100, seed=1)
     prob = P.Problem.from_lp(lp)

@@ -1,0 +1,205 @@
+"""The learned warm start through the C ABI: features, forward, backward and Adam of the HIP
+kernels against the FP64 oracle (oracle.mlp, itself pinned against torch.nn / torch.optim and
+finite differences), training on trajectories of the plain GPU IPM, and the gain of the
+trained network over the zero-start CG it falls back to.
+
+Tolerances: the kernels compute in FP32 on FP32 inputs; the oracle computes in FP64 on the
+same (FP32-representable) values. Gradients: norm-wise relative error <= 1e-5 per parameter
+block and elementwise error <= 1e-3 of the block's largest entry.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+from oracle import ipm as oipm
+from oracle import mlp as omlp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P = None
+L = None
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    global P, L
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2209_08722_amd as mod
+    import paper_2209_08722_amd.learned as learned
+    P, L = mod, learned
+    c = mod.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to("cuda:0", dtype=dtype) if dtype else t.to("cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _theta(n_in, H, n_out, seed):
+    th = lpgen.mlp_init(n_in, H, n_out, seed, out_scale=0.5)
+    return f32(th + 0.05 * np.random.default_rng(seed + 1).standard_normal(th.size))
+
+
+@pytest.mark.parametrize("m,n", [(7, 100), (37, 10007), (500, 100000), (1, 3)])
+def test_features_parity(ctx, m, n):
+    rng = np.random.default_rng(m + n)
+    dy = rng.standard_normal(m) * 1e-3
+    x = np.exp(rng.uniform(-12, 6, n))
+    s = np.exp(rng.uniform(-6, 12, n))
+    f = host(L.ipm_mlp_features(ctx, dev(dy), dev(x), dev(s), 17, 200))
+    ref = omlp.features(dy, x, s, 17, 200)
+    assert f.shape == ref.shape
+    # FP32 rounding of FP64 values; bins of the histogram decided in FP64 on both sides
+    assert np.all(np.abs(f - ref) <= 2e-7 * np.maximum(1.0, np.abs(ref)))
+
+
+def test_features_constant_column_ratio(ctx):
+    """x / s constant: zero spread, every quantile equals the value."""
+    n, m = 1000, 5
+    x = np.full(n, 3.0)
+    s = np.full(n, 1.5)
+    f = host(L.ipm_mlp_features(ctx, dev(np.ones(m)), dev(x), dev(s), 0, 200))
+    ref = omlp.features(np.ones(m), x, s, 0, 200)
+    assert np.allclose(f, ref, rtol=2e-7, atol=1e-12)
+    assert np.all(f[m + 5:m + 17] == f[m + 3])
+
+
+@pytest.mark.parametrize("m,H,B", [(5, 7, 3), (37, 64, 5), (500, 256, 64), (2000, 256, 3), (130, 100, 130)])
+def test_forward_parity(ctx, m, H, B):
+    n_in = m + omlp.N_EXTRA
+    th = _theta(n_in, H, m, m)
+    X = f32(np.random.default_rng(B).standard_normal((B, n_in)))
+    net = L.Mlp(n_in, H, m, th)
+    Y = host(L.ipm_mlp_forward(ctx, net, dev(X, torch.float32)))
+    ref, _ = omlp.forward(th, X, H, m)
+    assert np.linalg.norm(Y - ref) <= 1e-5 * np.linalg.norm(ref)
+    assert np.max(np.abs(Y - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("m,H,B", [(5, 7, 3), (37, 64, 5), (500, 256, 64), (2000, 256, 16)])
+def test_backward_parity(ctx, m, H, B):
+    n_in = m + omlp.N_EXTRA
+    th = _theta(n_in, H, m, 2 * m)
+    rng = np.random.default_rng(3 * B)
+    X = f32(rng.standard_normal((B, n_in)))
+    T = f32(rng.standard_normal((B, m)))
+    net = L.Mlp(n_in, H, m, th)
+    loss = L.ipm_mlp_backward(ctx, net, dev(X, torch.float32), dev(T, torch.float32))
+    g = host(net.grad)
+    lref, gref = omlp.backward(th, X, T, H, m)
+    assert loss == pytest.approx(lref, rel=1e-5)
+    parts = omlp.unpack(g, n_in, H, m)
+    rparts = omlp.unpack(gref, n_in, H, m)
+    for name in parts:
+        a, r = parts[name], rparts[name]
+        assert np.linalg.norm(a - r) <= 1e-5 * np.linalg.norm(r) + 1e-30, name
+        assert np.max(np.abs(a - r)) <= 1e-3 * np.max(np.abs(r)) + 1e-30, name
+
+
+def test_adam_parity(ctx):
+    m, H = 20, 32
+    n_in = m + omlp.N_EXTRA
+    th = _theta(n_in, H, m, 4)
+    net = L.Mlp(n_in, H, m, th)
+    rng = np.random.default_rng(9)
+    ref, m1, m2 = th.copy(), np.zeros_like(th), np.zeros_like(th)
+    for t in range(1, 6):
+        g = f32(rng.standard_normal(th.size) * 10.0 ** rng.uniform(-4, 0, th.size))
+        net.grad.copy_(dev(g, torch.float32))
+        L.ipm_mlp_adam(ctx, net, 1e-2)
+        ref, m1, m2 = omlp.adam(ref, g, m1, m2, t, 1e-2)
+    got = host(net.params)
+    assert np.linalg.norm(got - ref) <= 1e-6 * np.linalg.norm(ref)
+    # FP32 parameters: each of the 5 updates rounds p (6e-8 relative) and the update (1e-5 of lr)
+    assert np.max(np.abs(got - ref)) <= 1e-6 * max(1.0, np.max(np.abs(ref))) + 5 * 1e-5 * 1e-2
+
+
+def test_target_parity(ctx):
+    rng = np.random.default_rng(13)
+    prev, dy = rng.standard_normal(333), rng.standard_normal(333)
+    t = host(L.ipm_mlp_target(ctx, dev(prev), dev(dy)))
+    ref = omlp.target(prev, dy)
+    assert np.max(np.abs(t - ref)) <= 2e-7 * np.max(np.abs(ref))
+
+
+def test_predict_parity(ctx):
+    m, H, n = 50, 64, 3001
+    n_in = m + omlp.N_EXTRA
+    th = _theta(n_in, H, m, 5)
+    rng = np.random.default_rng(11)
+    dy = rng.standard_normal(m) * 7.0
+    x, s = np.exp(rng.uniform(-8, 4, n)), np.exp(rng.uniform(-4, 8, n))
+    net = L.Mlp(n_in, H, m, th)
+    got = host(L.ipm_mlp_predict(ctx, net, dev(dy), dev(x), dev(s), 9, 200))
+    # the oracle takes the FP32-rounded features, as the network does
+    f = f32(omlp.features(dy, x, s, 9, 200))
+    y, _ = omlp.forward(th, f[None, :], H, m)
+    ref = np.linalg.norm(dy) * y[0]
+    assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
+def test_training_reduces_the_loss(ctx):
+    """Adam on a learnable synthetic map (targets a fixed linear function of the inputs)."""
+    m, H, N = 30, 64, 512
+    n_in = m + omlp.N_EXTRA
+    rng = np.random.default_rng(12)
+    X = f32(rng.standard_normal((N, n_in)))
+    Wt = rng.standard_normal((m, n_in)) / np.sqrt(n_in)
+    T = f32(X @ Wt.T)
+    net = L.Mlp(n_in, H, m, lpgen.mlp_init(n_in, H, m, 0))
+    Xd, Td = dev(X, torch.float32), dev(T, torch.float32)
+    l0 = L.evaluate(ctx, net, Xd, Td)
+    hist = L.train(ctx, net, Xd, Td, epochs=100, batch=64, lr=3e-3, seed=0)
+    # the loss is a mean log error: a drop by log(5) is a fivefold smaller (geometric mean) error
+    assert hist[-1] < l0 - np.log(5.0)
+
+
+def _family(seeds, m=40, n=4000):
+    return [lpgen.illcond_lp(m, n, seed=sd, matrix_seed=1000, cond=1e4, storage="f64") for sd in seeds]
+
+
+def test_learned_warm_start_gain(ctx):
+    """Trained on plain-IPM trajectories of 24 LPs that share an ill-conditioned A (different
+    b, c), the network cuts the held-out LPs' total CG iterations below the zero-start CG's,
+    at the same accuracy (same optimum, same stop test)."""
+    m, n, H, w = 40, 4000, 256, 160
+    params = P.Params(w=w, s=2, seed=0)
+    train_lps = _family(range(24), m, n)
+    test_lps = _family(range(24, 32), m, n)
+    data = L.collect(ctx, [P.Problem.from_lp(lp) for lp in train_lps], params)
+    held = L.collect(ctx, [P.Problem.from_lp(lp) for lp in test_lps], params)
+    net = L.Mlp(m + omlp.N_EXTRA, H, m, lpgen.mlp_init(m + omlp.N_EXTRA, H, m, 0, out_scale=1.0))
+    l0, h0 = L.evaluate(ctx, net, data.X, data.T), L.evaluate(ctx, net, held.X, held.T)
+    hist = L.train(ctx, net, data.X, data.T, epochs=100, batch=64, lr=1e-4, seed=0)
+    h1 = L.evaluate(ctx, net, held.X, held.T)
+    cold_it = learn_it = prev_it = 0
+    for lp in test_lps:
+        prob = P.Problem.from_lp(lp)
+        cold = P.solve(ctx, prob, params)
+        lrn = P.solve(ctx, prob, params, net=net)
+        prev = P.solve(ctx, prob, P.Params(w=w, s=2, seed=0, warm_start=P.IPM_WARM_PREV))
+        assert cold.converged and lrn.converged and prev.converged
+        oc, ol = float(lp.c @ host(cold.state.x)), float(lp.c @ host(lrn.state.x))
+        assert abs(oc - ol) <= 1e-8 * (1 + abs(oc))
+        cold_it += sum(i["pcg_iters"] for i in cold.infos)
+        learn_it += sum(i["pcg_iters"] for i in lrn.infos)
+        prev_it += sum(i["pcg_iters"] for i in prev.infos)
+    print(f"\nlearned warm start: {data.X.shape[0]} samples, train loss {l0:.3f} -> {hist[-1]:.3f}, "
+          f"held-out loss {h0:.3f} -> {h1:.3f}; held-out CG iterations: zero start {cold_it}, "
+          f"previous dy {prev_it}, network {learn_it} "
+          f"({100.0 * (cold_it - learn_it) / cold_it:.1f}% fewer than zero start)")
+    assert hist[-1] < l0
+    assert learn_it < cold_it

@@ -300,6 +300,49 @@ def test_pcg_warm_start_never_increases_the_energy_error():
             assert e <= best * (1 + 1e-9)
 
 
+def test_pcg_two_candidates_span_the_solution():
+    """Two candidates whose span holds the solution give it exactly: no CG iteration."""
+    lp = lpgen.tiny_lp(15, 400, 13)
+    rng = np.random.default_rng(7)
+    d2 = np.exp(rng.uniform(-3, 3, lp.n))
+    M, L, _ = _sketched(lp, d2, 60, 2, 3)
+    p = rng.standard_normal(lp.m)
+    xs = np.linalg.solve(M, p)
+    v1 = rng.standard_normal(lp.m)
+    v2 = 2.5 * xs - 0.7 * v1
+    res = ipm.pcg(lambda v: M @ v, L, p, tol=1e-10, maxit=100, dy0=np.stack([v1, v2], axis=1))
+    assert res.warm_used and res.iters == 0
+    assert np.allclose(res.dy, xs, rtol=1e-8)
+
+
+def test_pcg_two_candidates_beat_each_alone():
+    """The two-candidate start is the M-norm best point of the plane (brute force over a grid)
+    and so no worse than either candidate's best multiple."""
+    lp = lpgen.tiny_lp(15, 400, 14)
+    rng = np.random.default_rng(8)
+    d2 = np.exp(rng.uniform(-3, 3, lp.n))
+    M, L, _ = _sketched(lp, d2, 60, 2, 4)
+    p = rng.standard_normal(lp.m)
+    xs = np.linalg.solve(M, p)
+    enorm = lambda e: np.sqrt(e @ M @ e)
+    for t in range(10):
+        v1 = xs + rng.standard_normal(lp.m) * np.linalg.norm(xs) * rng.uniform(0.1, 2)
+        v2 = xs * rng.uniform(-1, 1) + rng.standard_normal(lp.m) * np.linalg.norm(xs)
+        two = ipm.pcg(lambda v: M @ v, L, p, tol=1e-10, maxit=0, dy0=np.stack([v1, v2], axis=1))
+        e2 = enorm(two.dy - xs)
+        for v in (v1, v2):
+            one = ipm.pcg(lambda u: M @ u, L, p, tol=1e-10, maxit=0, dy0=v)
+            assert e2 <= enorm(one.dy - xs) * (1 + 1e-10)
+        grid = np.linspace(-3, 3, 121)
+        best = min(enorm(a * v1 + b * v2 - xs) for a in grid for b in grid)
+        assert e2 <= best * (1 + 1e-10)
+    # parallel candidates fall back to the first one's best multiple
+    v1 = rng.standard_normal(lp.m)
+    par = ipm.pcg(lambda v: M @ v, L, p, tol=1e-10, maxit=0, dy0=np.stack([v1, -2 * v1], axis=1))
+    one = ipm.pcg(lambda v: M @ v, L, p, tol=1e-10, maxit=0, dy0=v1)
+    assert par.warm_used == one.warm_used and np.allclose(par.dy, one.dy, rtol=1e-12)
+
+
 # ------------------------------------------------------------------ step lengths (Algorithm 3, steps 6-7)
 
 def _constraints(x, s, dx, ds, gamma, mu0, r0n, rn, a):

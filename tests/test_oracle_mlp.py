@@ -31,8 +31,11 @@ def _torch_model(theta, n_in, H, n_out):
 def _torch_loss(lin, X, T, n_out):
     h = torch.relu(lin[0](X))
     h = torch.relu(lin[1](h))
-    y = X[:, :n_out] + lin[2](h)
-    return (((y - T) ** 2).sum(1) / (T * T).sum(1)).mean(), y
+    y = lin[2](h)
+    # the loss as a minimisation over the scale, solved by torch's least squares
+    beta = torch.linalg.lstsq(y[:, :, None], T[:, :, None]).solution[:, 0, 0]
+    e = ((beta[:, None] * y - T) ** 2).sum(1) / (T * T).sum(1)
+    return torch.log(e + mlp.EPS).mean(), y
 
 
 @pytest.mark.parametrize("n_out,H,B", [(5, 7, 3), (30, 16, 8), (50, 64, 1)])
@@ -134,15 +137,13 @@ def test_features_layout_and_statistics():
     assert f[-1] == 7 / 200
 
 
-def test_untrained_output_layer_returns_previous_direction():
-    """With W3 = 0 and b3 = 0 the skip makes the initial iterate the previous direction."""
-    m, H = 12, 16
-    theta = lpgen.mlp_init(m + mlp.N_EXTRA, H, m, 0)
-    P = mlp.unpack(theta, m + mlp.N_EXTRA, H, m)
-    P["W3"][:] = 0.0
-    P["b3"][:] = 0.0
+def test_target_completes_the_previous_direction():
+    """The target is orthogonal to the previous direction, and the previous direction and the
+    target span the new direction (least squares over the pair leaves no residual)."""
     rng = np.random.default_rng(8)
-    dy = rng.standard_normal(m)
-    x, s = rng.uniform(0.5, 2, 100), rng.uniform(0.5, 2, 100)
-    out = mlp.predict(theta, dy, x, s, 3, 200, H)
-    assert np.allclose(out, dy, rtol=1e-14)
+    prev, dy = rng.standard_normal(12), rng.standard_normal(12)
+    t = mlp.target(prev, dy)
+    assert abs(t @ prev) <= 1e-13 * np.linalg.norm(t) * np.linalg.norm(prev)
+    V = np.stack([prev, t], axis=1)
+    c, *_ = np.linalg.lstsq(V, dy, rcond=None)
+    assert np.linalg.norm(V @ c - dy) <= 1e-12 * np.linalg.norm(dy)
