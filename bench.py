@@ -81,6 +81,115 @@ def cpu_baseline(lp, budget_s: float):
                       f"(dense Cholesky of A D^2 A^T) FP64 IPM, {el:.1f} s wall"}
 
 
+def timed_solve(P, ctx, prob, prm, net=None, timing=False):
+    """One full solve from x = s = 1, y = 0, wall-clocked between device synchronizations."""
+    import torch
+    torch.cuda.synchronize()
+    if timing:
+        ctx.set_timing(True)
+    t0 = time.perf_counter()
+    res = P.solve(ctx, prob, prm, net=net)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {}
+    if timing:
+        for name, kid in (("matvec64", P.native.IPM_KERNEL_MATVEC), ("matvec32", P.native.IPM_KERNEL_MATVEC32),
+                          ("resid64", P.native.IPM_KERNEL_RESID64), ("sketch", P.native.IPM_KERNEL_SKETCH),
+                          ("gram", P.native.IPM_KERNEL_GRAM)):
+            kt[name] = ctx.kernel_time(kid)
+        ctx.set_timing(False)
+    last = res.infos[-1]
+    steps = [i for i in res.infos if i["rc"] != P.IPM_CONVERGED]
+    return {
+        "converged": bool(res.converged), "iterations": res.iterations, "seconds": el,
+        "iter_per_s": res.iterations / el if el > 0 else None,
+        "cg_iterations": int(sum(i["pcg_iters"] for i in steps)),
+        "refine_rounds": int(sum(i["refine_rounds"] for i in steps)),
+        "warm_kept": int(sum(i["warm_used"] for i in steps)),
+        "final_relgap": last["relgap"], "final_rp_rel": last["rp_rel"], "final_rd_rel": last["rd_rel"],
+        "objective": last["obj"], "kernels": kt,
+    }
+
+
+def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
+    """Plain FP64 form vs the mixed-precision form with the learned warm start on one held-out LP
+    of an LP family, both solved to the same stop test; the network is trained first (untimed)
+    on plain-form trajectories of the family's training seeds."""
+    import torch
+    from lpgen import device as gdev
+    from paper_2209_08722_amd import learned as L
+    if which == "3":
+        m, n, w, s, storage = 2000, 200_000, 8000, 2, "f32"
+        make = lambda sd: gdev.illcond_lp(m, n, seed=sd, storage=storage)
+        desc = ("ill-conditioned A = U diag(sigma) V^T, 2000x200000, sigma log-spaced 1..1e4, FP32 storage "
+                "(FP64 copy for the plain form), w=8000 s=2")
+        test_seed = 64
+    else:
+        m, n, w, s, storage = 2000, 2_000_000, 16000, 2, "bf16"
+        make = lambda sd: gdev.dense_lp(m, n, seed=sd, storage=storage)
+        desc = "dense 2000x2000000 A iid N(0,1), BF16 storage (FP64 copy for the plain form), w=16000 s=2"
+        test_seed = 64
+    prm_plain = P.Params(w=w, s=s, seed=0)
+    prm_mixed = P.Params(w=w, s=s, seed=0, precision=P.IPM_MIXED)
+
+    def problems(lp):
+        low = P.Problem(P.Matrix(lp.A, lp.n), lp.b, lp.c)
+        wide = P.Problem(P.Matrix(lp.A64, lp.n), lp.b, lp.c)
+        return low, wide
+
+    log(f"forms: training the warm-start network on {train_seeds} plain-form solves ({desc})")
+    t0 = time.perf_counter()
+    feats, targs = [], []
+    for sd in range(train_seeds):
+        lp = make(sd)
+        _, wide = problems(lp)
+        tr = L.collect(ctx, [wide], prm_plain)
+        feats.append(tr.X)
+        targs.append(tr.T)
+        log(f"forms: training seed {sd}: {tr.iterations} IPM iterations, {tr.cg_iterations} CG iterations")
+        del lp, wide
+    X, T = torch.cat(feats), torch.cat(targs)
+    net = L.Mlp(m + L.N_EXTRA, 256, m, __import__("lpgen").mlp_init(m + L.N_EXTRA, 256, m, 0, out_scale=1.0))
+    l0 = L.evaluate(ctx, net, X, T)
+    hist = L.train(ctx, net, X, T, epochs=epochs, batch=64, lr=1e-4, seed=0)
+    t_train = time.perf_counter() - t0
+    log(f"forms: {X.shape[0]} samples, loss {l0:.3f} -> {hist[-1]:.3f} in {t_train:.1f} s")
+
+    lp = make(test_seed)
+    low, wide = problems(lp)
+    out = {"workload": desc, "m": m, "n": n, "w": w, "s": s, "test_seed": test_seed,
+           "training": {"seeds": train_seeds, "samples": int(X.shape[0]), "epochs": epochs,
+                        "loss_first": l0, "loss_last": hist[-1], "seconds": t_train}}
+    runs = [("plain_fp64", wide, prm_plain, None), ("mixed", low, prm_mixed, None),
+            ("mixed_prev", low, P.Params(w=w, s=s, seed=0, precision=P.IPM_MIXED, warm_start=P.IPM_WARM_PREV), None),
+            ("mixed_learned", low, prm_mixed, net),
+            ("mixed_f32acc", low, P.Params(w=w, s=s, seed=0, precision=P.IPM_MIXED_F32ACC), None)]
+    for name, prob, prm, nt in runs:
+        timed_solve(P, ctx, prob, prm, net=nt)            # warm-up: workspaces, code paths
+        r = timed_solve(P, ctx, prob, prm, net=nt)        # wall clock, no per-kernel events
+        if name in ("plain_fp64", "mixed_learned"):
+            r["kernels"] = timed_solve(P, ctx, prob, prm, net=nt, timing=True)["kernels"]
+        log(f"forms: {name}: {r['iterations']} iterations in {r['seconds']:.3f} s "
+            f"({r['iter_per_s']:.2f} it/s), CG {r['cg_iterations']}, obj {r['objective']:.12e}")
+        out[name] = r
+    ref = out["plain_fp64"]["objective"]
+    for name, *_ in runs:
+        out[name]["objective_rel_diff_vs_plain"] = abs(out[name]["objective"] - ref) / (1 + abs(ref))
+    out["speedup_mixed_learned_vs_plain"] = out["mixed_learned"]["iter_per_s"] / out["plain_fp64"]["iter_per_s"]
+    out["time_to_gap_ratio"] = out["plain_fp64"]["seconds"] / out["mixed_learned"]["seconds"]
+    # matvec bandwidth of the low-precision inner matvec (algorithmic bytes: A once + d^2)
+    ms, cnt = out["mixed_learned"]["kernels"]["matvec64"]
+    esz = 4 if storage == "f32" else 2
+    if cnt:
+        out["matvec_lowprec_storage_hbm_gbps"] = (m * n * esz + n * 8) / (ms / cnt * 1e-3) / 1e9
+    ms, cnt = out["plain_fp64"]["kernels"]["matvec64"]
+    if cnt:
+        out["matvec_fp64_hbm_gbps"] = (m * n * 8 + n * 8) / (ms / cnt * 1e-3) / 1e9
+    del low, wide, lp
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +198,10 @@ def main() -> int:
     ap.add_argument("--workload", default="1", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="3", choices=["3", "4d", "none"],
+                    help="workload of the plain vs mixed+learned comparison")
+    ap.add_argument("--train-seeds", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -156,6 +269,7 @@ def main() -> int:
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     mv_ms, mv_n = ctx.kernel_time(P.native.IPM_KERNEL_MATVEC)
+    gpu_seconds = el
     sk_ms, sk_n = ctx.kernel_time(P.native.IPM_KERNEL_SKETCH)
     gr_ms, gr_n = ctx.kernel_time(P.native.IPM_KERNEL_GRAM)
     ctx.set_timing(False)
@@ -207,6 +321,8 @@ def main() -> int:
         "gram_tflops": gr_tf,
         "gram_mfma_frac": (gr_tf / FP64_MFMA_PEAK_TFLOPS) if gr_tf else None,
     }
+    if args.forms != "none":
+        out["forms"] = forms_comparison(P, ctx, args.forms, args.train_seeds, args.epochs)
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle) for ~{args.cpu_budget:.0f} s")
         out["cpu_baseline"] = cpu_baseline(lp, args.cpu_budget)

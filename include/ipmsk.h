@@ -88,7 +88,7 @@ typedef struct {
 /* Method parameters. ipm_params_default() fills the values used throughout:
  * sigma 0.5 (Section 7), gamma 0.9, theta 0.9999, tol_pcg 1e-10, gap_tol 1e-8,
  * min_step 1e-14, maxit_pcg 500, stag_window 10, stag_ratio 0.99, max_redraws 3, vcorr 1,
- * precision IPM_PLAIN, warm_start IPM_WARM_NONE, inner_tol 1e-4, max_refine 12. */
+ * precision IPM_PLAIN, warm_start IPM_WARM_NONE, inner_tol 1e-4, max_refine 12, max_shifts 3. */
 typedef struct {
     double sigma;        /* centering parameter, in (0, 4/5) (Algorithm 3 input)            */
     double gamma;        /* neighbourhood parameter, in (0, 1)                              */
@@ -103,25 +103,34 @@ typedef struct {
     int32_t stag_window;
     int32_t max_redraws; /* extra draws of W (doubled w, s >= 2) after a failed solve      */
     int32_t vcorr;       /* 1: perturbation v of eq. compv; 0: v = 0                         */
-    int32_t precision;   /* IPM_PLAIN: FP64 accumulation everywhere. IPM_MIXED: the sketch
-                            accumulates in FP32 (B stored FP32) and CG runs as iterative
+    int32_t precision;   /* A is read in its storage type (F64, F32 or BF16) by every form.
+                            IPM_PLAIN: FP64 accumulation everywhere, B stored FP64.
+                            IPM_MIXED: the sketch accumulates in FP32 and B is stored FP32
+                            (the Gram widens it to an FP64 Q); the CG matvecs accumulate in
+                            FP64, which costs nothing on these bandwidth-bound passes and
+                            keeps the plain form's CG iteration counts.
+                            IPM_MIXED_F32ACC: as IPM_MIXED, and the CG runs as iterative
                             refinement: inner CG with FP32-accumulated matvecs to inner_tol,
                             outer residual p - A D^2 A^T dy recomputed with FP64 accumulation,
-                            stop on ||L^-1 r|| <= tol_pcg ||L^-1 p|| for that true residual     */
+                            stop on ||L^-1 r|| <= tol_pcg ||L^-1 p|| for that true residual.
+                            The Cholesky, the residuals and the step stay FP64 in all forms.  */
     int32_t warm_start;  /* IPM_WARM_NONE | IPM_WARM_PREV (previous iteration's dy) |
                             IPM_WARM_GIVEN (ipm_step_warm's candidates). The initial iterate
                             is the combination of the candidate vectors closest to the
                             solution in the M-norm (M = A D^2 A^T; for one candidate v it is
                             (v^T p / v^T M v) v), kept only if its preconditioned residual
                             beats that of dy = 0                                              */
-    double inner_tol;    /* relative tolerance of each inner CG solve (mixed form)           */
-    int32_t max_refine;  /* refinement rounds (mixed form)                                   */
-    int32_t reserved;
+    double inner_tol;    /* relative tolerance of each inner CG solve (IPM_MIXED_F32ACC)     */
+    int32_t max_refine;  /* refinement rounds (IPM_MIXED_F32ACC)                             */
+    int32_t max_shifts;  /* when Q = B B^T fails to factor: retries with Q + delta_j I,
+                            delta_j = 2^-53 trace(Q) 100^j, j < max_shifts, before the next
+                            draw of W (the FP64 Gram squares the condition of B)              */
     uint64_t seed;       /* sketch seed                                                     */
 } ipm_params;
 
 #define IPM_PLAIN 0
 #define IPM_MIXED 1
+#define IPM_MIXED_F32ACC 2
 #define IPM_WARM_NONE 0
 #define IPM_WARM_PREV 1
 #define IPM_WARM_GIVEN 2
@@ -149,6 +158,7 @@ typedef struct {
     int32_t refine_rounds;     /* mixed form: outer refinement rounds                      */
     int32_t warm_used;         /* 1 if the warm start was kept                              */
     double dy_norm;            /* ||dy|| of the accepted direction                          */
+    double shift;              /* delta added to Q's diagonal for the accepted draw (0: none) */
 } ipm_step_info;
 
 /* ---- context ------------------------------------------------------------------------------ */
@@ -186,9 +196,9 @@ int ipm_precond_factor(ipm_ctx* ctx, int64_t m, int32_t w, int32_t b_dtype, cons
                        double* L, double* Linv, int64_t* bad_pivot);
 
 /* Preconditioned CG for A D^2 A^T dy = p with preconditioner Q = L L^T (Algorithm 1, step 3).
- * params->precision selects the plain form (FP64 accumulation) or the mixed form (iterative
- * refinement around FP32-accumulated inner solves, see ipm_params.precision); A's storage type
- * is used as given in both.
+ * params->precision IPM_MIXED_F32ACC runs iterative refinement around FP32-accumulated inner
+ * solves (see ipm_params.precision); the other forms run one CG with FP64-accumulated
+ * matvecs. A's storage type is used as given.
  *   d2   [device] n doubles, the diagonal of D^2
  *   Linv [device] m x m lower triangle of L^{-1} (as written by ipm_precond_factor)
  *   p    [device] m doubles

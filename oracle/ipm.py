@@ -70,6 +70,7 @@ class Params:
     stag_ratio: float = 0.99
     min_step: float = 1e-14
     max_redraws: int = 3
+    max_shifts: int = 3
 
 
 @dataclass
@@ -322,6 +323,31 @@ def sketch_seed(seed: int, attempt: int) -> int:
 
 # ---------------------------------------------------------------- one IPM iteration
 
+def shifted_cholesky(Q: np.ndarray, max_shifts: int):
+    """Cholesky factor of Q, or of Q + delta I when Q's factorization breaks down.
+
+    Q = B B^T formed in FP64 squares the condition number of B = A D W, so a Q whose B is
+    still numerically full rank can fail to factor; Algorithm 1 takes Q^{-1/2} from the SVD of
+    B, which has no such loss. On breakdown the shift delta_j = u trace(Q) 100^j
+    (u = 2^-53, j = 0 .. max_shifts-1; trace(Q) >= ||Q||_2, so delta_0 is the rounding level of
+    Q's largest entries) is tried in turn. Returns (L, delta), delta = 0 without a shift, or
+    (None, 0) when every shift fails.
+    """
+    try:
+        return sla.cholesky(Q, lower=True), 0.0
+    except np.linalg.LinAlgError:
+        pass
+    m = Q.shape[0]
+    base = np.finfo(float).eps / 2 * float(np.trace(Q))
+    for j in range(max_shifts):
+        delta = base * 100.0 ** j
+        try:
+            return sla.cholesky(Q + delta * np.eye(m), lower=True), delta
+        except np.linalg.LinAlgError:
+            continue
+    return None, 0.0
+
+
 def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
          keep: bool = False) -> tuple:
     """One iteration of Algorithm 3 from state ``st``; returns (new_state, StepInfo).
@@ -366,9 +392,8 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
             key = sketch_seed(prm.seed, attempt)
             B = sketch_ADW(A, np.sqrt(d2), w, sk, key, st.k)
             Q = B @ B.T
-            try:
-                L = sla.cholesky(Q, lower=True)
-            except np.linalg.LinAlgError:
+            L, shift = shifted_cholesky(Q, prm.max_shifts)
+            if L is None:
                 if attempt == prm.max_redraws:
                     info.status = ERR_NOT_SPD
                     info.extra.update(attempts=attempt + 1)
@@ -378,7 +403,7 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
                       stag_window=prm.stag_window, stag_ratio=prm.stag_ratio)
             if res.status in (OK, ERR_BREAKDOWN):
                 break
-        info.extra.update(attempts=attempt + 1, w_used=w, s_used=sk)
+        info.extra.update(attempts=attempt + 1, w_used=w, s_used=sk, shift=shift)
         info.pcg_iters, info.pcg_status, info.pcg_relres = res.iters, res.status, res.relres
         if res.status == ERR_BREAKDOWN:
             info.status = ERR_BREAKDOWN

@@ -13,14 +13,14 @@ from dataclasses import dataclass, field
 from typing import Optional
 
 from . import native
-from .native import (IPM_BF16, IPM_CONVERGED, IPM_F32, IPM_F64, IPM_MIXED, IPM_OK, IPM_PLAIN,
+from .native import (IPM_BF16, IPM_CONVERGED, IPM_F32, IPM_F64, IPM_MIXED, IPM_MIXED_F32ACC, IPM_OK, IPM_PLAIN,
                      IPM_WARM_GIVEN, IPM_WARM_NONE, IPM_WARM_PREV, IpmMatrix, IpmParams, IpmPcgInfo,
                      IpmProblem, IpmState, IpmStepInfo)
 
 __all__ = ["IpmError", "Context", "Matrix", "Problem", "State", "Params", "ipm_sketch",
            "ipm_precond_factor", "ipm_pcg_solve", "ipm_step", "ipm_step_warm", "ipm_last_dy",
            "ipm_normal_matvec", "solve", "IPM_OK", "IPM_CONVERGED", "IPM_F64", "IPM_F32", "IPM_BF16",
-           "IPM_PLAIN", "IPM_MIXED", "IPM_WARM_NONE", "IPM_WARM_PREV", "IPM_WARM_GIVEN"]
+           "IPM_PLAIN", "IPM_MIXED", "IPM_MIXED_F32ACC", "IPM_WARM_NONE", "IPM_WARM_PREV", "IPM_WARM_GIVEN"]
 
 
 def _torch():
@@ -185,16 +185,17 @@ class Params:
     stag_window: int = 10
     max_redraws: int = 3
     vcorr: int = 1
-    precision: int = IPM_PLAIN     # IPM_PLAIN or IPM_MIXED
+    precision: int = IPM_PLAIN     # IPM_PLAIN, IPM_MIXED or IPM_MIXED_F32ACC
     warm_start: int = IPM_WARM_NONE
     inner_tol: float = 1e-4
     max_refine: int = 12
+    max_shifts: int = 3
 
     def c(self) -> IpmParams:
         return IpmParams(self.sigma, self.gamma, self.theta, self.tol_pcg, self.gap_tol, self.min_step,
                          self.stag_ratio, self.w, self.s, self.maxit_pcg, self.stag_window, self.max_redraws,
-                         self.vcorr, self.precision, self.warm_start, self.inner_tol, self.max_refine, 0,
-                         self.seed & ((1 << 64) - 1))
+                         self.vcorr, self.precision, self.warm_start, self.inner_tol, self.max_refine,
+                         self.max_shifts, self.seed & ((1 << 64) - 1))
 
 
 def ipm_normal_matvec(ctx: Context, A: Matrix, d2, v):

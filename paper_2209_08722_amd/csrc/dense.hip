@@ -188,6 +188,20 @@ __global__ void k_fill(double* p, int64_t count, double v) {
         p[i] = v;
 }
 
+// out = sum_i A[i][i] (one block, fixed summation order).
+__global__ __launch_bounds__(256) void k_diag_sum(const double* __restrict__ A, int m, int lda, double* out) {
+    __shared__ double sh[4];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) a += A[(int64_t)i * lda + i];
+    const double t = block_sum(a, sh);
+    if (threadIdx.x == 0) *out = t;
+}
+
+__global__ void k_diag_add(double* A, int m, int lda, double delta) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < m) A[(int64_t)i * lda + i] += delta;
+}
+
 __global__ void k_fill_i32(int* p, int64_t count, int v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -243,6 +257,16 @@ hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t st) {
     int64_t blocks = (count + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_sum(const double* A, int m, int lda, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_sum, dim3(1), dim3(256), 0, st, A, m, lda, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_add(double* A, int m, int lda, double delta, hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_add, dim3((m + 255) / 256), dim3(256), 0, st, A, m, lda, delta);
     return hipGetLastError();
 }
 

@@ -203,8 +203,10 @@ int do_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* dvals, int is_d2,
     return IPM_OK;
 }
 
-// Q = B B^T (lower), Q = L L^T in place in Lw, X = L^{-1}. Returns the first bad pivot or -1.
-int do_factor(ipm_ctx* ctx, int m, int w, int b_f64, const void* B, double* Lw, double* X, int64_t* bad) {
+// Q = B B^T (lower) plus delta I, Q = L L^T in place in Lw, X = L^{-1}. *bad receives the
+// first bad pivot or -1 and *trace the trace of B B^T.
+int factor_once(ipm_ctx* ctx, int m, int w, int b_f64, const void* B, double* Lw, double* X, double delta,
+                int64_t* bad, double* trace) {
     hipStream_t st = ctx->stream;
     const int T = (m + 63) / 64;
     const int tiles = T * (T + 1) / 2;
@@ -223,7 +225,10 @@ int do_factor(ipm_ctx* ctx, int m, int w, int b_f64, const void* B, double* Lw, 
         t.stop();
     }
     int* status = nullptr;
-    CHK(ws(ctx, W_STATUS, 4, &status));
+    CHK(ws(ctx, W_STATUS, 8, &status));
+    double* tr = reinterpret_cast<double*>(status + 2);
+    HIPCHK(launch_diag_sum(Lw, m, m, tr, st));
+    if (delta > 0.0) HIPCHK(launch_diag_add(Lw, m, m, delta, st));
     HIPCHK(launch_fill_i32(status, 1, INT_MAX, st));
     HIPCHK(launch_fill(X, (int64_t)m * m, 0.0, st));
     for (int k0 = 0; k0 < m; k0 += 64) {
@@ -253,10 +258,29 @@ int do_factor(ipm_ctx* ctx, int m, int w, int b_f64, const void* B, double* Lw, 
                             X + (int64_t)r0 * m, m, 1, st));
     }
     int* hs = reinterpret_cast<int*>(ctx->pinned);
-    HIPCHK(hipMemcpyAsync(hs, status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hs, status, 2 * sizeof(int) + sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     resolve_timing(ctx, IPM_KERNEL_GRAM, INT_MAX);
     *bad = (hs[0] == INT_MAX) ? -1 : hs[0];
+    *trace = *reinterpret_cast<double*>(hs + 2);
+    return IPM_OK;
+}
+
+// Factor Q = B B^T; on breakdown retry with Q + delta_j I, delta_j = u trace(Q) 100^j
+// (u = 2^-53, j < max_shifts; trace(Q) >= ||Q||_2): forming B B^T in FP64 squares the
+// condition number of B, and a shift of the order of the Gram's own rounding error restores a
+// factorization where B is still numerically of full rank. *shift receives the delta used.
+int do_factor(ipm_ctx* ctx, int m, int w, int b_f64, const void* B, double* Lw, double* X, int max_shifts,
+              int64_t* bad, double* shift) {
+    double trace = 0.0;
+    *shift = 0.0;
+    CHK(factor_once(ctx, m, w, b_f64, B, Lw, X, 0.0, bad, &trace));
+    double delta = 0x1p-53 * trace;
+    for (int j = 0; *bad >= 0 && j < max_shifts; ++j, delta *= 100.0) {
+        double t2 = 0.0;
+        CHK(factor_once(ctx, m, w, b_f64, B, Lw, X, delta, bad, &t2));
+        if (*bad < 0) *shift = delta;
+    }
     return IPM_OK;
 }
 
@@ -536,10 +560,12 @@ int check_solver_params(ipm_ctx* ctx, const ipm_params* p) {
     if (p->stag_window < 1) return fail(ctx, IPM_ERR_ARG, "stag_window must be >= 1");
     if (!(p->tol_pcg >= 0 && is_finite(p->tol_pcg))) return fail(ctx, IPM_ERR_ARG, "bad tol_pcg");
     if (!(p->stag_ratio > 0 && is_finite(p->stag_ratio))) return fail(ctx, IPM_ERR_ARG, "bad stag_ratio");
-    if (p->precision != IPM_PLAIN && p->precision != IPM_MIXED) return fail(ctx, IPM_ERR_ARG, "bad precision");
+    if (p->precision != IPM_PLAIN && p->precision != IPM_MIXED && p->precision != IPM_MIXED_F32ACC)
+        return fail(ctx, IPM_ERR_ARG, "bad precision");
     if (p->warm_start < IPM_WARM_NONE || p->warm_start > IPM_WARM_GIVEN) return fail(ctx, IPM_ERR_ARG, "bad warm_start");
     if (!(p->inner_tol > 0 && p->inner_tol < 1)) return fail(ctx, IPM_ERR_ARG, "inner_tol must be in (0, 1)");
     if (p->max_refine < 1 || p->max_refine > 1000) return fail(ctx, IPM_ERR_ARG, "max_refine out of range");
+    if (p->max_shifts < 0 || p->max_shifts > 8) return fail(ctx, IPM_ERR_ARG, "max_shifts out of range");
     return IPM_OK;
 }
 
@@ -585,6 +611,7 @@ void ipm_params_default(ipm_params* p) {
     p->warm_start = IPM_WARM_NONE;
     p->inner_tol = 1e-4;
     p->max_refine = 12;
+    p->max_shifts = 3;
     p->seed = 0;
 }
 
@@ -678,7 +705,8 @@ int ipm_precond_factor(ipm_ctx* ctx, int64_t m, int32_t w, int32_t b_dtype, cons
     double* Lw = L;
     if (!Lw) CHK(ws(ctx, W_L, (size_t)m * m, &Lw));
     int64_t bad = -1;
-    CHK(do_factor(ctx, (int)m, w, b_dtype == IPM_F64, B, Lw, Linv, &bad));
+    double shift = 0.0;
+    CHK(do_factor(ctx, (int)m, w, b_dtype == IPM_F64, B, Lw, Linv, 0, &bad, &shift));
     if (bad_pivot) *bad_pivot = bad;
     if (bad >= 0) return fail(ctx, IPM_ERR_NOT_SPD, "Q is not positive definite (pivot %lld)", (long long)bad);
     return IPM_OK;
@@ -692,7 +720,7 @@ int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const dou
     CHK(check_solver_params(ctx, params));
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
     PcgOut o{};
-    if (params->precision == IPM_MIXED) {
+    if (params->precision == IPM_MIXED_F32ACC) {
         const int m = (int)A->m;
         const double* dy0 = nullptr;
         if (warm) {
@@ -748,7 +776,8 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
     hipStream_t st = ctx->stream;
     const int m = (int)A->m;
-    const bool mixed = prm->precision == IPM_MIXED;
+    const bool mixed = prm->precision != IPM_PLAIN;            // FP32 sketch, B and Gram input
+    const bool refine = prm->precision == IPM_MIXED_F32ACC;    // FP32-accumulated inner CG
     const int64_t n = A->n;
     const int Gn = pointwise_blocks(n);
 
@@ -851,6 +880,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
     int w_used = prm->w, s_used = prm->s;
     PcgOut po{};
     int attempts = 0;
+    double shift = 0.0;
     for (int a = 0; a <= prm->max_redraws; ++a) {
         attempts = a + 1;
         w_used = prm->w << a;
@@ -859,7 +889,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         hk = make_keys(seed_a, state->k, w_used, s_used);
         CHK(do_sketch(ctx, A, d2, 1, hk, w_used, mixed ? 0 : 1, B));
         int64_t bad = -1;
-        CHK(do_factor(ctx, m, w_used, mixed ? 0 : 1, B, Lw, X, &bad));
+        CHK(do_factor(ctx, m, w_used, mixed ? 0 : 1, B, Lw, X, prm->max_shifts, &bad, &shift));
         if (bad >= 0) {
             if (a == prm->max_redraws) {
                 info->attempts = attempts;
@@ -868,7 +898,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
             }
             continue;
         }
-        if (mixed) {
+        if (refine) {
             CHK(do_pcg_mixed(ctx, A, d2, X, p, dyv, dy0, ncand, prm, &po));
         } else {
             PcgCfg cfg{prm->tol_pcg, prm->maxit_pcg, 1, false, &ctx->last_pcg_iters};
@@ -888,6 +918,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
     info->pcg_relres = po.relres;
     info->refine_rounds = po.rounds;
     info->warm_used = po.warm_used;
+    info->shift = shift;
 
     // directions (eq. ipm_inf): ds, true residual, v, dx
     {

@@ -91,6 +91,8 @@ hipError_t launch_potrf_diag(double* Lw, int64_t ld, int k0, int kb, double* X, 
                              hipStream_t st);
 hipError_t launch_transpose(const double* X, double* XT, int m, hipStream_t st);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t st);
+hipError_t launch_diag_sum(const double* A, int m, int lda, double* out, hipStream_t st);
+hipError_t launch_diag_add(double* A, int m, int lda, double delta, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st);
 
 // ---- PCG -----------------------------------------------------------------------------------------

@@ -28,7 +28,7 @@ IPM_ERR_NOMEM = -6
 IPM_F64, IPM_F32, IPM_BF16 = 0, 1, 2
 IPM_DENSE_ROWMAJOR = 0
 IPM_KERNEL_MATVEC, IPM_KERNEL_SKETCH, IPM_KERNEL_GRAM, IPM_KERNEL_MATVEC32, IPM_KERNEL_RESID64 = 0, 1, 2, 3, 4
-IPM_PLAIN, IPM_MIXED = 0, 1
+IPM_PLAIN, IPM_MIXED, IPM_MIXED_F32ACC = 0, 1, 2
 IPM_WARM_NONE, IPM_WARM_PREV, IPM_WARM_GIVEN = 0, 1, 2
 
 STATUS_NAMES = {
@@ -58,7 +58,7 @@ class IpmParams(ctypes.Structure):
                 ("gap_tol", c_double), ("min_step", c_double), ("stag_ratio", c_double),
                 ("w", c_int32), ("s", c_int32), ("maxit_pcg", c_int32), ("stag_window", c_int32),
                 ("max_redraws", c_int32), ("vcorr", c_int32), ("precision", c_int32), ("warm_start", c_int32),
-                ("inner_tol", c_double), ("max_refine", c_int32), ("reserved", c_int32), ("seed", c_uint64)]
+                ("inner_tol", c_double), ("max_refine", c_int32), ("max_shifts", c_int32), ("seed", c_uint64)]
 
 
 class IpmPcgInfo(ctypes.Structure):
@@ -72,7 +72,7 @@ class IpmStepInfo(ctypes.Structure):
                 ("mu", c_double), ("gap", c_double), ("relgap", c_double), ("rp_rel", c_double),
                 ("rd_rel", c_double), ("obj", c_double), ("alpha_max", c_double), ("alpha", c_double),
                 ("pcg_relres", c_double), ("vnorm", c_double), ("refine_rounds", c_int32), ("warm_used", c_int32),
-                ("dy_norm", c_double)]
+                ("dy_norm", c_double), ("shift", c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -1,11 +1,13 @@
-"""The mixed-precision form and the warm starts of the HIP library, through its C ABI, against
+"""The mixed-precision forms and the warm starts of the HIP library, through its C ABI, against
 the FP64 oracle.
 
-Mixed form: A is stored in FP32 or BF16 (the stored values define the LP, so both sides solve
-the same problem), the inner CG matvecs accumulate in FP32, and the CG stop test is applied to
-the residual recomputed with FP64 accumulation. The bar is therefore the plain method's: the
-paper's preconditioned residual (eq. pdcond2) recomputed by the oracle below tol_pcg, and the
-LP optimum within 1e-8. The FP64-oracle error of each result is printed.
+Mixed forms: A is stored in FP32 or BF16 (the stored values define the LP, so both sides solve
+the same problem) and the sketch B is accumulated and stored in FP32. IPM_MIXED runs one CG
+with FP64-accumulated matvecs; IPM_MIXED_F32ACC accumulates the inner CG matvecs in FP32 and
+applies the stop test to the residual recomputed with FP64 accumulation (iterative
+refinement). The bar is the plain method's: the paper's preconditioned residual (eq. pdcond2)
+recomputed by the oracle below tol_pcg, and the LP optimum within 1e-8. The FP64-oracle error
+of each result is printed.
 """
 import numpy as np
 import pytest
@@ -71,7 +73,7 @@ def _case(m, n, w, s, storage, seed, spread=5.0):
 def test_pcg_mixed_meets_the_fp64_residual_bound(ctx, m, n, w, storage):
     A, d2, L, p = _case(m, n, w, 2, storage, seed=m + n)
     Linv = np.tril(np.linalg.inv(L))
-    prm = P.Params(w=w, s=2, precision=P.IPM_MIXED)
+    prm = P.Params(w=w, s=2, precision=P.IPM_MIXED_F32ACC)
     Am = P.Matrix.from_numpy(A, dtype=tdtype(storage))
     dy, info = P.ipm_pcg_solve(ctx, Am, dev(d2), dev(Linv), dev(p), prm)
     dy = host(dy)
@@ -96,13 +98,31 @@ def test_pcg_mixed_meets_the_fp64_residual_bound(ctx, m, n, w, storage):
         assert info["rounds"] >= 2    # FP32 inner solves alone cannot reach 1e-10
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_pcg_fp64_accumulation_on_low_storage(ctx, storage):
+    """IPM_MIXED's CG: one solve with FP64-accumulated matvecs over the stored values, the same
+    iterates as the plain CG on the widened matrix."""
+    A, d2, L, p = _case(500, 20011, 2000, 2, storage, seed=11)
+    Linv = dev(np.tril(np.linalg.inv(L)))
+    dy, info = P.ipm_pcg_solve(ctx, P.Matrix.from_numpy(A, dtype=tdtype(storage)), dev(d2), Linv, dev(p),
+                               P.Params(w=2000, s=2, precision=P.IPM_MIXED))
+    dyw, infow = P.ipm_pcg_solve(ctx, P.Matrix.from_numpy(A), dev(d2), Linv, dev(p), P.Params(w=2000, s=2))
+    assert info["rounds"] == 1 and abs(info["iters"] - infow["iters"]) <= 1
+    M = (A * d2) @ A.T
+    f = sla.solve_triangular(L, M @ host(dy) - p, lower=True)
+    assert np.linalg.norm(f) <= 1e-10 * 1.01 * np.linalg.norm(sla.solve_triangular(L, p, lower=True))
+    e = host(dy) - host(dyw)
+    assert np.sqrt(e @ M @ e) <= 1e-8 * np.sqrt(host(dyw) @ M @ host(dyw))
+
+
 def test_pcg_mixed_plain_iteration_budget(ctx):
     """The mixed form's total inner CG count stays within a small factor of the plain count."""
     A, d2, L, p = _case(500, 20011, 2000, 2, "bf16", seed=3)
     Linv = dev(np.tril(np.linalg.inv(L)))
     Am = P.Matrix.from_numpy(A, dtype=torch.bfloat16)
     _, plain = P.ipm_pcg_solve(ctx, Am, dev(d2), Linv, dev(p), P.Params(w=2000, s=2))
-    _, mixed = P.ipm_pcg_solve(ctx, Am, dev(d2), Linv, dev(p), P.Params(w=2000, s=2, precision=P.IPM_MIXED))
+    _, mixed = P.ipm_pcg_solve(ctx, Am, dev(d2), Linv, dev(p),
+                               P.Params(w=2000, s=2, precision=P.IPM_MIXED_F32ACC))
     print(f"plain {plain['iters']} mixed {mixed['iters']} in {mixed['rounds']} rounds")
     assert mixed["iters"] <= 2 * plain["iters"] + 10
 
@@ -113,7 +133,7 @@ def test_pcg_mixed_warm_start(ctx):
     M = (A * d2) @ A.T
     xs = np.linalg.solve(M, p)
     Am = P.Matrix.from_numpy(A, dtype=torch.bfloat16)
-    prm = P.Params(w=200, s=2, precision=P.IPM_MIXED)
+    prm = P.Params(w=200, s=2, precision=P.IPM_MIXED_F32ACC)
     good = xs * (1 + 1e-6 * np.random.default_rng(0).standard_normal(xs.size))
     dw, iw = P.ipm_pcg_solve(ctx, Am, dev(d2), Linv, dev(p), prm, dy0=dev(good))
     _, ic = P.ipm_pcg_solve(ctx, Am, dev(d2), Linv, dev(p), prm)
@@ -155,22 +175,27 @@ def _lockstep(ctx, lp, oprm, gprm, steps, rtol_state):
     print(f"mixed lockstep {lp.name}: worst relative state error {worst:.3e}")
 
 
+PREC = {"mixed": "IPM_MIXED", "f32acc": "IPM_MIXED_F32ACC"}
+
+
+@pytest.mark.parametrize("prec", ["mixed", "f32acc"])
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_step_lockstep_mixed(ctx, storage):
+def test_step_lockstep_mixed(ctx, storage, prec):
     lp = lpgen.dense_lp(50, 2000, seed=0, storage=storage)
     oprm = oipm.Params(w=200, s=2, seed=1)
-    gprm = P.Params(w=200, s=2, seed=1, precision=P.IPM_MIXED)
+    gprm = P.Params(w=200, s=2, seed=1, precision=getattr(P, PREC[prec]))
     # both sides solve to the same preconditioned residual; the directions differ by at most
     # that much, amplified by the step's sensitivity, so states agree far below the stop tolerance
     _lockstep(ctx, lp, oprm, gprm, steps=10, rtol_state=1e-7)
 
 
+@pytest.mark.parametrize("prec", ["mixed", "f32acc"])
 @pytest.mark.parametrize("m,n,w,storage,seed", [(50, 2000, 200, "f32", 0), (50, 2000, 200, "bf16", 1),
                                                 (23, 1003, 92, "bf16", 5), (300, 20000, 1200, "f32", 2)])
-def test_solve_mixed_matches_oracle(ctx, m, n, w, storage, seed):
+def test_solve_mixed_matches_oracle(ctx, m, n, w, storage, seed, prec):
     lp = lpgen.dense_lp(m, n, seed=seed, storage=storage)
     prob = P.Problem.from_lp(lp, dtype=tdtype(storage))
-    res = P.solve(ctx, prob, P.Params(w=w, s=2, seed=seed, precision=P.IPM_MIXED))
+    res = P.solve(ctx, prob, P.Params(w=w, s=2, seed=seed, precision=getattr(P, PREC[prec])))
     ores = oipm.solve(lp.A, lp.b, lp.c, oipm.Params(w=w, s=2, seed=seed), "exact")
     assert res.converged and ores.converged
     x = host(res.state.x)
@@ -192,11 +217,11 @@ def test_solve_mixed_matches_oracle(ctx, m, n, w, storage, seed):
 
 # ------------------------------------------------------------------------- warm starts
 
-@pytest.mark.parametrize("precision", ["plain", "mixed"])
+@pytest.mark.parametrize("precision", ["plain", "mixed", "f32acc"])
 def test_solve_warm_prev(ctx, precision):
-    lp = lpgen.dense_lp(50, 2000, seed=2, storage="bf16" if precision == "mixed" else "f64")
+    lp = lpgen.dense_lp(50, 2000, seed=2, storage="f64" if precision == "plain" else "bf16")
     prob = P.Problem.from_lp(lp, dtype=tdtype(lp.storage))
-    prec = P.IPM_MIXED if precision == "mixed" else P.IPM_PLAIN
+    prec = getattr(P, PREC[precision]) if precision in PREC else P.IPM_PLAIN
     cold = P.solve(ctx, prob, P.Params(w=200, s=2, precision=prec))
     warm = P.solve(ctx, prob, P.Params(w=200, s=2, precision=prec, warm_start=P.IPM_WARM_PREV))
     assert cold.converged and warm.converged
@@ -237,7 +262,7 @@ def test_step_warm_given_matches_oracle(ctx):
     assert ginfo["dy_norm"] == pytest.approx(np.linalg.norm(dy), rel=1e-12)
 
 
-@pytest.mark.parametrize("precision", ["plain", "mixed"])
+@pytest.mark.parametrize("precision", ["plain", "mixed", "f32acc"])
 def test_step_two_candidates_matches_oracle(ctx, precision):
     """Two candidates whose span holds the Newton solution: both sides start from it (no CG
     iteration) and take the same step."""
@@ -245,7 +270,7 @@ def test_step_two_candidates_matches_oracle(ctx, precision):
     prob = P.Problem.from_lp(lp, dtype=tdtype(lp.storage))
     oprm = oipm.Params(w=160, s=2, seed=4)
     gprm = P.Params(w=160, s=2, seed=4, warm_start=P.IPM_WARM_GIVEN,
-                    precision=P.IPM_MIXED if precision == "mixed" else P.IPM_PLAIN)
+                    precision=getattr(P, PREC[precision]) if precision in PREC else P.IPM_PLAIN)
     st = oipm.initial_state(lp.A, lp.b, lp.c)
     for _ in range(4):
         st, _ = oipm.step(lp.A, lp.b, lp.c, st, oprm, "sketch")

@@ -343,6 +343,29 @@ def test_pcg_two_candidates_beat_each_alone():
     assert par.warm_used == one.warm_used and np.allclose(par.dy, one.dy, rtol=1e-12)
 
 
+def test_shifted_cholesky_special_cases():
+    """SPD Q: the plain factor (library routine). Q = B B^T with B of numerical rank < m: the
+    factor of Q + delta I with delta = u trace(Q) 100^j. A Q with a large negative eigenvalue:
+    none."""
+    rng = np.random.default_rng(9)
+    B = rng.standard_normal((20, 60))
+    Q = B @ B.T
+    L, d = ipm.shifted_cholesky(Q, 2)
+    assert d == 0.0 and np.allclose(L, np.linalg.cholesky(Q), rtol=1e-13, atol=1e-13)
+    U, _ = np.linalg.qr(rng.standard_normal((20, 20)))
+    sv = np.logspace(0, -12, 20)
+    B = (U * sv) @ rng.standard_normal((20, 60)) / np.sqrt(60)
+    B[5] = B[4]                                   # an exactly repeated row: Q is singular
+    Q = B @ B.T
+    L, d = ipm.shifted_cholesky(Q, 2)
+    assert L is not None and d > 0.0
+    assert d in (np.finfo(float).eps / 2 * np.trace(Q) * f for f in (1.0, 100.0))
+    assert np.linalg.norm(L @ L.T - (Q + d * np.eye(20))) <= 1e-14 * np.linalg.norm(Q)
+    Qn = Q - 1e-3 * np.trace(Q) * np.outer(U[:, 0], U[:, 0])
+    L, d = ipm.shifted_cholesky(Qn, 2)
+    assert L is None
+
+
 # ------------------------------------------------------------------ step lengths (Algorithm 3, steps 6-7)
 
 def _constraints(x, s, dx, ds, gamma, mu0, r0n, rn, a):
