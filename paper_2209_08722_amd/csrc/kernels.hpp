@@ -19,12 +19,13 @@ enum RowPost { POST_PLAIN = 0, POST_MATVEC = 1, POST_RESID = 2, POST_RHAT = 3, P
 enum StripKind { STRIP_MATVEC = 0, STRIP_RESID = 1, STRIP_DIR = 2 };
 
 struct StripPlan {
-    int nt;        // threads per block (256 or 1024)
+    int nt;        // threads per block
     int rpt;       // rows per thread (template instance)
     int grid;      // blocks (persistent)
     int nstrips;   // column strips of width sw
     int sw;        // strip width in columns
     size_t lds;    // dynamic LDS bytes
+    int lpr;       // lanes per row segment
 };
 
 // Arguments of every strip pass. Unused pointers may be null. launch_strip queues the pass and

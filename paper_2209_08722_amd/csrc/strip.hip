@@ -318,6 +318,7 @@ StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind) {
     (void)kind;
     StripPlan p{};
     const int vec = dtype == 0 ? 2 : (dtype == 1 ? 4 : 8);
+    p.lpr = kLpr;
     p.sw = kLpr * vec;
     p.nstrips = (int)((n + p.sw - 1) / p.sw);
     // rows per thread: the smallest instance covering m; 256-thread blocks (2 per CU, measured
