@@ -26,6 +26,8 @@ struct StripPlan {
     int sw;        // strip width in columns
     size_t lds;    // dynamic LDS bytes
     int lpr;       // lanes per row segment
+    int rr;        // experimental re-read variant (0 in the library)
+    int kk;        // rows per thread of the re-read variant
 };
 
 // Arguments of every strip pass. Unused pointers may be null. launch_strip queues the pass and
@@ -67,7 +69,7 @@ int rowsum_blocks(int m);
 constexpr int kStripMaxGrid = 4096;
 
 // ---- sketch and perturbation -----------------------------------------------------------------
-struct SketchPlan { int rows_per_block; int chunks; int64_t cols_per_chunk; size_t lds; bool atomic; bool global_only; };
+struct SketchPlan { int rows_per_block; int chunks; int64_t cols_per_chunk; size_t lds; bool atomic; bool global_only; int range_width; };
 SketchPlan sketch_plan(int m, int64_t n, int w, int out_f64, int num_cu);
 hipError_t launch_sketch(int dtype, const void* A, int m, int64_t n, int64_t ld, const double* dvals,
                          int dvals_are_d2, const HashKeys& hk, int w, int out_f64, void* B,

@@ -4,16 +4,19 @@
 // Sketch: a block owns R rows of A and a range of columns. Its threads stream along the rows
 // (consecutive threads read consecutive columns, so every load is coalesced), hash each column
 // once into its s buckets and signs, and scatter-add sign * d_j * A[i][j] / sqrt(s) into an
-// LDS-resident R x w bucket array with LDS atomics. When one block covers all columns of its
-// rows the bucket array is stored to B; otherwise blocks add their arrays into B with global
-// atomics. W is never stored: the hash is recomputed wherever W is applied.
+// LDS-resident R x w bucket array with LDS atomics. The buckets accumulate in FP64 whatever the
+// type of B (FP64 LDS atomics measured several times faster than FP32 ones on gfx950 for this
+// random scatter). When one block covers all columns of its rows the bucket array is stored to B
+// (converted to B's type); otherwise blocks add their arrays into B with global atomics. W is
+// never stored: the hash is recomputed wherever W is applied.
 #include "kernels.hpp"
 
 namespace ipmsk {
 
 namespace {
 
-constexpr int SNT = 256;
+constexpr int SNT = 1024;     // 16 waves per block: the LDS bucket array limits blocks per CU, so
+                              // the block itself must carry enough waves to hide load latency
 constexpr int SUNROLL = 4;    // columns per thread per pass (independent loads in flight)
 
 template <typename T, typename BT, int R>
@@ -21,16 +24,16 @@ __global__ __launch_bounds__(SNT) void k_sketch_lds(const T* __restrict__ A, int
                                                     const double* __restrict__ dv, int d_is_d2, HashKeys hk, int w,
                                                     int64_t cpc, BT* __restrict__ B, int atomic) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    BT* bk = reinterpret_cast<BT*>(smem_raw);   // [R][w]
+    double* bk = reinterpret_cast<double*>(smem_raw);   // [R][w]
     const int tid = threadIdx.x;
     const int row0 = blockIdx.x * R;
     const int64_t jb = (int64_t)blockIdx.y * cpc;
     const int64_t je = (jb + cpc < n) ? jb + cpc : n;
-    for (int i = tid; i < R * w; i += SNT) bk[i] = (BT)0;
+    for (int i = tid; i < R * w; i += SNT) bk[i] = 0.0;
     __syncthreads();
     const int s = hk.s;
     for (int64_t jj = jb + tid; jj < je; jj += (int64_t)SNT * SUNROLL) {
-        BT av[SUNROLL][R];
+        double av[SUNROLL][R];
         double dj[SUNROLL];
 #pragma unroll
         for (int u = 0; u < SUNROLL; ++u) {
@@ -41,7 +44,7 @@ __global__ __launch_bounds__(SNT) void k_sketch_lds(const T* __restrict__ A, int
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 const int i = row0 + rr;
-                av[u][rr] = (ok && i < m) ? (BT)Elem<T>::load1(A + (int64_t)i * ld + j) : (BT)0;
+                av[u][rr] = (ok && i < m) ? (double)Elem<T>::load1(A + (int64_t)i * ld + j) : 0.0;
             }
         }
 #pragma unroll
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(SNT) void k_sketch_lds(const T* __restrict__ A, int
                 int bucket;
                 double sign;
                 w_entry(hk, r, (uint64_t)j, bucket, sign);
-                const BT coef = (BT)(sign * dj[u] * hk.scale);
+                const double coef = sign * dj[u] * hk.scale;
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr) atomicAdd(&bk[rr * w + bucket], coef * av[u][rr]);
             }
@@ -64,30 +67,52 @@ __global__ __launch_bounds__(SNT) void k_sketch_lds(const T* __restrict__ A, int
         const int i = row0 + rr;
         if (i < m) {
             BT* dst = B + (int64_t)i * w + bcol;
-            if (atomic) unsafeAtomicAdd(dst, bk[idx]);
-            else *dst = bk[idx];
+            if (atomic) unsafeAtomicAdd(dst, (BT)bk[idx]);
+            else *dst = (BT)bk[idx];
         }
     }
 }
 
-// Fallback when one row of buckets does not fit in LDS: scatter straight into B with global
-// atomics (B zeroed first).
+// Wide sketches (a row of buckets larger than LDS): a block owns one row of A and one range of
+// at most `wb` buckets inside the bucket block of one copy r (copy r only ever lands in
+// [r w/s, (r+1) w/s)). It streams the whole row, hashes copy r of each column and keeps the
+// columns whose bucket falls in its range, accumulating them in LDS (FP64); the range is then
+// stored to B. Each row is read once per range.
 template <typename T, typename BT>
-__global__ __launch_bounds__(SNT) void k_sketch_global(const T* __restrict__ A, int m, int64_t n, int64_t ld,
-                                                       const double* __restrict__ dv, int d_is_d2, HashKeys hk,
-                                                       int w, BT* __restrict__ B) {
-    const int i = blockIdx.y;
-    for (int64_t j = (int64_t)blockIdx.x * SNT + threadIdx.x; j < n; j += (int64_t)gridDim.x * SNT) {
-        const double dd = dv[j];
-        const double djv = d_is_d2 ? sqrt(dd) : dd;
-        const double a = (double)Elem<T>::load1(A + (int64_t)i * ld + j);
-        for (int r = 0; r < hk.s; ++r) {
+__global__ __launch_bounds__(SNT) void k_sketch_range(const T* __restrict__ A, int m, int64_t n, int64_t ld,
+                                                      const double* __restrict__ dv, int d_is_d2, HashKeys hk,
+                                                      int w, int wb, int ranges_per_copy, BT* __restrict__ B) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* bk = reinterpret_cast<double*>(smem_raw);   // [wb]
+    const int i = blockIdx.x;
+    const int r = blockIdx.y / ranges_per_copy;
+    const int b0 = r * hk.blk + (blockIdx.y % ranges_per_copy) * wb;
+    const int b1 = min(b0 + wb, (r + 1) * hk.blk);
+    for (int b = threadIdx.x; b < b1 - b0; b += SNT) bk[b] = 0.0;
+    __syncthreads();
+    const T* row = A + (int64_t)i * ld;
+    for (int64_t jj = threadIdx.x; jj < n; jj += (int64_t)SNT * SUNROLL) {
+        double av[SUNROLL], dj[SUNROLL];
+#pragma unroll
+        for (int u = 0; u < SUNROLL; ++u) {
+            const int64_t j = jj + (int64_t)u * SNT;
+            const bool ok = j < n;
+            const double dd = ok ? dv[j] : 0.0;
+            dj[u] = d_is_d2 ? sqrt(dd) : dd;
+            av[u] = ok ? (double)Elem<T>::load1(row + j) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < SUNROLL; ++u) {
+            const int64_t j = jj + (int64_t)u * SNT;
+            if (j >= n) continue;
             int bucket;
             double sign;
             w_entry(hk, r, (uint64_t)j, bucket, sign);
-            unsafeAtomicAdd(&B[(int64_t)i * w + bucket], (BT)(sign * djv * hk.scale * a));
+            if (bucket >= b0 && bucket < b1) atomicAdd(&bk[bucket - b0], sign * dj[u] * hk.scale * av[u]);
         }
     }
+    __syncthreads();
+    for (int b = threadIdx.x; b < b1 - b0; b += SNT) B[(int64_t)i * w + b0 + b] = (BT)bk[b];
 }
 
 template <typename T, typename BT, int R>
@@ -104,9 +129,10 @@ hipError_t sketch_type(const void* Av, int m, int64_t n, int64_t ld, const doubl
     const T* A = reinterpret_cast<const T*>(Av);
     BT* B = reinterpret_cast<BT*>(Bv);
     if (sp.global_only) {
-        int gx = (int)((n + SNT - 1) / SNT);
-        if (gx > 64) gx = 64;
-        IPM_LAUNCH((k_sketch_global<T, BT>), dim3(gx, m), dim3(SNT), 0, st, A, m, n, ld, dv, d2, hk, w, B);
+        const int blk = w / hk.s;
+        const int rpc = (blk + sp.range_width - 1) / sp.range_width;
+        IPM_LAUNCH((k_sketch_range<T, BT>), dim3(m, hk.s * rpc), dim3(SNT), sp.lds, st, A, m, n, ld, dv, d2, hk, w,
+                   sp.range_width, rpc, B);
         return hipGetLastError();
     }
     switch (sp.rows_per_block) {
@@ -176,13 +202,23 @@ __global__ __launch_bounds__(256) void k_dx(int64_t n, const double* __restrict_
 
 SketchPlan sketch_plan(int m, int64_t n, int w, int out_f64, int num_cu) {
     SketchPlan sp{};
-    const size_t esz = out_f64 ? 8 : 4;
+    (void)out_f64;
+    const size_t esz = 8;   // LDS buckets accumulate in FP64 for either type of B
     const size_t budget_small = 64 * 1024, budget_max = 160 * 1024;
     int R = 0;
     for (int r : {8, 4, 2, 1})
         if ((size_t)r * w * esz <= budget_small && r <= m) { R = r; break; }
     if (R == 0 && (size_t)w * esz <= budget_max) R = 1;
-    if (R == 0) { sp.global_only = true; sp.atomic = true; sp.chunks = 1; sp.cols_per_chunk = n; return sp; }
+    if (R == 0) {
+        // one row per block and a bucket range of at most 160 KB of FP64 buckets
+        sp.global_only = true;
+        sp.atomic = false;
+        sp.chunks = 1;
+        sp.cols_per_chunk = n;
+        sp.range_width = (int)(budget_max / esz);
+        sp.lds = (size_t)sp.range_width * esz;
+        return sp;
+    }
     sp.rows_per_block = R;
     const int row_blocks = (m + R - 1) / R;
     const int target = 2 * num_cu;
