@@ -193,8 +193,10 @@ def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
+    # defaults: one full solve (48 iterations on the 500 x 100000 LP) of warm-up, then two full
+    # solves timed, so the rate is the whole-solve average rather than that of a phase of it
+    ap.add_argument("--steps", type=int, default=96)
+    ap.add_argument("--warmup", type=int, default=48)
     ap.add_argument("--workload", default="1", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -264,7 +266,7 @@ def main() -> int:
     for i in range(args.steps):
         info = one_step()
         pcg_iters.append(info["pcg_iters"])
-        if (i + 1) % 10 == 0:
+        if (i + 1) % 24 == 0:
             log(f"  step {i + 1}/{args.steps}")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0

@@ -26,8 +26,8 @@ struct StripPlan {
     int sw;        // strip width in columns
     size_t lds;    // dynamic LDS bytes
     int lpr;       // lanes per row segment
-    int rr;        // experimental re-read variant (0 in the library)
-    int kk;        // rows per thread of the re-read variant
+    int rr;        // 1: re-read form (k_strip_rr)
+    int kk;        // rows per thread of the re-read form (a multiple of its chunk)
 };
 
 // Arguments of every strip pass. Unused pointers may be null. launch_strip queues the pass and

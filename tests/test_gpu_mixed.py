@@ -191,7 +191,8 @@ def test_step_lockstep_mixed(ctx, storage, prec):
 
 @pytest.mark.parametrize("prec", ["mixed", "f32acc"])
 @pytest.mark.parametrize("m,n,w,storage,seed", [(50, 2000, 200, "f32", 0), (50, 2000, 200, "bf16", 1),
-                                                (23, 1003, 92, "bf16", 5), (300, 20000, 1200, "f32", 2)])
+                                                (23, 1003, 92, "bf16", 5), (300, 20000, 1200, "f32", 2),
+                                                (700, 15001, 2800, "bf16", 3)])
 def test_solve_mixed_matches_oracle(ctx, m, n, w, storage, seed, prec):
     lp = lpgen.dense_lp(m, n, seed=seed, storage=storage)
     prob = P.Problem.from_lp(lp, dtype=tdtype(storage))

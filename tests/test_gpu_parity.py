@@ -61,7 +61,8 @@ def test_normal_matvec_fp64(ctx, m, n):
 
 
 @pytest.mark.parametrize("m,n,dtype", [(60, 3001, "f32"), (60, 3001, "bf16"), (1500, 4003, "f64"),
-                                       (2000, 3001, "f32"), (2000, 5003, "bf16")])
+                                       (2000, 3001, "f32"), (2000, 5003, "bf16"), (513, 1999, "bf16"),
+                                       (1000, 1777, "bf16")])
 def test_normal_matvec_low_storage(ctx, m, n, dtype):
     A = rand_lp_matrix(m, n, 5)
     if dtype == "bf16":
