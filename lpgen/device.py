@@ -73,11 +73,12 @@ def _finish(A_vals, storage, seed, device, widen, name):
 
 
 def dense_lp(m: int, n: int, seed: int = 0, storage: str = "bf16", device: str = "cuda:0",
-             widen: bool = True) -> DeviceLP:
-    """A i.i.d. N(0, 1) rounded to ``storage`` (round to nearest even)."""
+             widen: bool = True, matrix_seed=None) -> DeviceLP:
+    """A i.i.d. N(0, 1) rounded to ``storage`` (round to nearest even), drawn from ``matrix_seed``
+    (default: ``seed``); (b, c) from ``seed``."""
     torch = _torch()
     g = torch.Generator(device=device)
-    g.manual_seed(seed)
+    g.manual_seed(seed if matrix_seed is None else matrix_seed)
     A = torch.randn((m, n), generator=g, dtype=torch.float32, device=device)
     return _finish(A, storage, seed, device, widen, f"dense{m}x{n}{storage}s{seed}")
 
