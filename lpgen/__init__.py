@@ -27,7 +27,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["LP", "dense_lp", "tiny_lp", "config", "bf16_round", "f32_round",
+__all__ = ["LP", "dense_lp", "sparse_lp", "tiny_lp", "config", "bf16_round", "f32_round",
            "CONFIGS", "mlp_init"]
 
 
@@ -93,6 +93,33 @@ def dense_lp(m: int, n: int, seed: int = 0, storage: str = "f64", name: str = ""
     return LP(A, b, c, x0, y0, s0, storage=storage, name=name or f"dense{m}x{n}s{seed}")
 
 
+def sparse_lp(m: int, n: int, density: float, seed: int = 0, storage: str = "f64", name: str = "") -> LP:
+    """Sparse LP, A in CSR (scipy.sparse.csr_matrix): round(density m n) positions drawn uniformly
+    without replacement, then one random row added to every column left empty (so no column of
+    A is zero); values N(0, 1) rounded to ``storage``. Draw order: pattern, fill rows, values,
+    then the witness pair."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    k = int(round(density * m * n))
+    flat = rng.choice(m * n, size=k, replace=False)
+    rows, cols = flat // n, flat % n
+    has = np.zeros(n, dtype=bool)
+    has[cols] = True
+    empty = np.flatnonzero(~has)
+    rows = np.concatenate([rows, rng.integers(0, m, size=empty.size)])
+    cols = np.concatenate([cols, empty])
+    vals = rng.standard_normal(rows.size)
+    if storage == "bf16":
+        vals = bf16_round(vals)
+    elif storage == "f32":
+        vals = f32_round(vals)
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    A.sum_duplicates()
+    A.sort_indices()
+    b, c, x0, y0, s0 = _witness(rng, A)
+    return LP(A, b, c, x0, y0, s0, storage=storage, name=name or f"sparse{m}x{n}s{seed}")
+
+
 def tiny_lp(m: int, n: int, seed: int) -> LP:
     """Small dense LP for brute-force checks (same recipe as ``dense_lp``)."""
     return dense_lp(m, n, seed, name=f"tiny{m}x{n}s{seed}")
@@ -122,17 +149,21 @@ def illcond_lp(m: int, n: int, seed: int = 0, matrix_seed: int = 1000,
 CONFIGS = {
     0: dict(m=50, n=2000, storage="f64", w=200, s=1, seeds=[0]),
     1: dict(m=500, n=100_000, storage="f64", w=2000, s=2, seeds=[0, 1, 2, 3, 4]),
+    2: dict(m=1000, n=1_000_000, storage="bf16", w=4000, s=2, seeds=[0], density=1e-3),
     3: dict(m=2000, n=200_000, storage="f32", w=8000, s=2, seeds=list(range(80))),
     "4d": dict(m=2000, n=2_000_000, storage="bf16", w=16000, s=2, seeds=[0]),
 }
 
 
 def config(i, seed: Optional[int] = None) -> LP:
-    """Build workload ``i`` (0, 1, 3 or "4d") at ``seed`` (defaults to its first seed)."""
+    """Build workload ``i`` (0, 1, 2, 3 or "4d") at ``seed`` (defaults to its first seed)."""
     cfg = CONFIGS[i]
     sd = cfg["seeds"][0] if seed is None else seed
     if i == 3:
         lp = illcond_lp(cfg["m"], cfg["n"], seed=sd, storage=cfg["storage"])
+    elif i == 2:
+        lp = sparse_lp(cfg["m"], cfg["n"], cfg["density"], seed=sd, storage=cfg["storage"],
+                       name=f"cfg2s{sd}")
     else:
         lp = dense_lp(cfg["m"], cfg["n"], seed=sd, storage=cfg["storage"],
                       name=f"cfg{i}s{sd}")

@@ -40,6 +40,7 @@ from typing import Callable, Optional
 
 import numpy as np
 import scipy.linalg as sla
+import scipy.sparse as sp
 
 from .sketch import sketch_ADW, sketch_matrix
 
@@ -110,6 +111,13 @@ def initial_state(A: np.ndarray, b: np.ndarray, c: np.ndarray) -> State:
     st.mu0 = float(st.x @ st.s / n)
     st.r0norm = float(np.sqrt(rp @ rp + rd @ rd))
     return st
+
+
+def normal_matrix(A, d2) -> np.ndarray:
+    """M = A diag(d2) A^T as a dense m x m array (A dense or scipy sparse)."""
+    if sp.issparse(A):
+        return (A.multiply(d2[None, :]).tocsr() @ A.T).toarray()
+    return (A * d2) @ A.T
 
 
 def residuals(A, b, c, x, y, s):
@@ -376,7 +384,7 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
 
     v = np.zeros(n)
     if mode == "exact":
-        Mmat = (A * d2) @ A.T
+        Mmat = normal_matrix(A, d2)
         try:
             L = sla.cholesky(Mmat, lower=True)
         except np.linalg.LinAlgError:

@@ -92,4 +92,6 @@ def sketch_ADW(A: np.ndarray, d: np.ndarray, w: int, s: int, seed: int, k: int) 
     A library sparse product serves as the step: (A diag(d)) times the sparse W.
     """
     W = sketch_matrix(A.shape[1], w, s, seed, k)
+    if sp.issparse(A):
+        return np.asarray((W.T @ A.multiply(d[None, :]).tocsr().T).T.toarray())
     return np.asarray((W.T @ (A * d).T).T)

@@ -366,6 +366,42 @@ def test_shifted_cholesky_special_cases():
     assert L is None
 
 
+def test_sparse_matrix_branches_match_dense():
+    """The sparse (CSR) branches of the oracle give what the dense ones give on the densified
+    matrix: normal matrix, sketch, and whole IPM steps."""
+    lp = lpgen.sparse_lp(30, 900, 0.05, seed=4)
+    Ad = lp.A.toarray()
+    rng = np.random.default_rng(3)
+    d2 = np.exp(rng.uniform(-3, 3, lp.n))
+    assert np.allclose(ipm.normal_matrix(lp.A, d2), ipm.normal_matrix(Ad, d2), rtol=1e-13, atol=1e-12)
+    assert np.allclose(sketch.sketch_ADW(lp.A, np.sqrt(d2), 120, 2, 5, 1),
+                       sketch.sketch_ADW(Ad, np.sqrt(d2), 120, 2, 5, 1), rtol=1e-13, atol=1e-13)
+    prm = ipm.Params(w=120, s=2, seed=2)
+    st_s = ipm.initial_state(lp.A, lp.b, lp.c)
+    st_d = ipm.initial_state(Ad, lp.b, lp.c)
+    for _ in range(5):     # direct-solver steps: identical up to summation order
+        st_s, _ = ipm.step(lp.A, lp.b, lp.c, st_s, prm, "exact")
+        st_d, _ = ipm.step(Ad, lp.b, lp.c, st_d, prm, "exact")
+        assert np.allclose(st_s.x, st_d.x, rtol=1e-11)
+    # one sketch step from the same point: CG counts may differ by one through rounding
+    new_s, inf_s = ipm.step(lp.A, lp.b, lp.c, st_s, prm, "sketch")
+    new_d, inf_d = ipm.step(Ad, lp.b, lp.c, st_s, prm, "sketch")
+    assert abs(inf_s.pcg_iters - inf_d.pcg_iters) <= 1
+    assert np.allclose(new_s.x, new_d.x, rtol=1e-7)
+
+
+def test_sparse_lp_optimum_matches_highs():
+    """Config-2-style sparse LP (uniform pattern, no empty column): the direct-solver IPM's
+    optimum equals HiGHS's."""
+    lp = lpgen.sparse_lp(40, 3000, 0.02, seed=6)
+    assert np.all(lp.A.getnnz(axis=0) > 0)
+    res = ipm.solve(lp.A, lp.b, lp.c, ipm.Params(), "exact")
+    assert res.converged
+    ref = linprog(lp.c, A_eq=lp.A, b_eq=lp.b, bounds=(0, None), method="highs")
+    obj = float(lp.c @ res.state.x)
+    assert abs(obj - ref.fun) <= 1e-8 * (1 + abs(ref.fun))
+
+
 # ------------------------------------------------------------------ step lengths (Algorithm 3, steps 6-7)
 
 def _constraints(x, s, dx, ds, gamma, mu0, r0n, rn, a):
