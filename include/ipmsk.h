@@ -55,15 +55,30 @@ extern "C" {
 #define IPM_F32   1
 #define IPM_BF16  2
 #define IPM_DENSE_ROWMAJOR 0
+#define IPM_CSR            1
 
 typedef struct ipm_ctx ipm_ctx;
 
-/* Constraint matrix A (m x n). val [device]: m*ld elements of `dtype`. */
+/* Constraint matrix A (m x n).
+ * IPM_DENSE_ROWMAJOR: val [device] m*ld elements of `dtype`; the sparse fields are ignored.
+ * IPM_CSR (the sparse LPs of Section 6): the nnz nonzeros twice, all [device]:
+ *   row order    val (nnz of `dtype`), row_ptr (m+1, int64), col_idx (nnz, int32, < n);
+ *   column order csc_val (nnz of `dtype`), col_ptr (n+1, int64), row_idx (nnz, int32, < m);
+ *   both orders hold the same values. ld is ignored and n must be below 2^31. The index arrays
+ *   are trusted: row_ptr / col_ptr must be non-decreasing from 0 to nnz and every index in
+ *   range (an index out of range is an out-of-bounds device access, not a returned error).
+ *   Duplicate entries are summed; the order within a row or column is free. */
 typedef struct {
     int64_t m, n, ld;
-    int32_t layout;          /* IPM_DENSE_ROWMAJOR */
+    int32_t layout;          /* IPM_DENSE_ROWMAJOR | IPM_CSR */
     int32_t dtype;           /* IPM_F64 | IPM_F32 | IPM_BF16 */
     const void* val;
+    int64_t nnz;
+    const int64_t* row_ptr;
+    const int32_t* col_idx;
+    const void* csc_val;
+    const int64_t* col_ptr;
+    const int32_t* row_idx;
 } ipm_matrix;
 
 /* LP data: b [device] m doubles, c [device] n doubles. */

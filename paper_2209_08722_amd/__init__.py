@@ -13,14 +13,14 @@ from dataclasses import dataclass, field
 from typing import Optional
 
 from . import native
-from .native import (IPM_BF16, IPM_CONVERGED, IPM_F32, IPM_F64, IPM_MIXED, IPM_MIXED_F32ACC, IPM_OK, IPM_PLAIN,
+from .native import (IPM_BF16, IPM_CONVERGED, IPM_CSR, IPM_F32, IPM_F64, IPM_MIXED, IPM_MIXED_F32ACC, IPM_OK, IPM_PLAIN,
                      IPM_WARM_GIVEN, IPM_WARM_NONE, IPM_WARM_PREV, IpmMatrix, IpmParams, IpmPcgInfo,
                      IpmProblem, IpmState, IpmStepInfo)
 
-__all__ = ["IpmError", "Context", "Matrix", "Problem", "State", "Params", "ipm_sketch",
+__all__ = ["IpmError", "Context", "Matrix", "SparseMatrix", "Problem", "State", "Params", "ipm_sketch",
            "ipm_precond_factor", "ipm_pcg_solve", "ipm_step", "ipm_step_warm", "ipm_last_dy",
            "ipm_normal_matvec", "solve", "IPM_OK", "IPM_CONVERGED", "IPM_F64", "IPM_F32", "IPM_BF16",
-           "IPM_PLAIN", "IPM_MIXED", "IPM_MIXED_F32ACC", "IPM_WARM_NONE", "IPM_WARM_PREV", "IPM_WARM_GIVEN"]
+           "IPM_CSR", "IPM_PLAIN", "IPM_MIXED", "IPM_MIXED_F32ACC", "IPM_WARM_NONE", "IPM_WARM_PREV", "IPM_WARM_GIVEN"]
 
 
 def _torch():
@@ -134,8 +134,47 @@ class Matrix:
 
 
 @dataclass
+class SparseMatrix:
+    """Sparse A (m x n) in device memory: CSR (val, row_ptr, col_idx) and a CSC mirror
+    (csc_val, col_ptr, row_idx) of the same nonzeros."""
+    m: int
+    n: int
+    val: object           # torch (nnz,) storage dtype, row order
+    row_ptr: object       # torch int64 (m + 1,)
+    col_idx: object       # torch int32 (nnz,)
+    csc_val: object       # torch (nnz,) storage dtype, column order
+    col_ptr: object       # torch int64 (n + 1,)
+    row_idx: object       # torch int32 (nnz,)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.val.shape[0])
+
+    def c(self) -> IpmMatrix:
+        return IpmMatrix(self.m, self.n, 0, IPM_CSR, _dtype_code(self.val), self.val.data_ptr(), self.nnz,
+                         self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.csc_val.data_ptr(),
+                         self.col_ptr.data_ptr(), self.row_idx.data_ptr())
+
+    @staticmethod
+    def from_scipy(A, dtype=None, device: int = 0) -> "SparseMatrix":
+        """A: any scipy.sparse matrix; its values are rounded to ``dtype`` (default float64)."""
+        import numpy as np
+        torch = _torch()
+        dtype = dtype or torch.float64
+        dev = f"cuda:{device}"
+        r = A.tocsr()
+        r.sum_duplicates()
+        cc = r.tocsc()
+        cc.sort_indices()
+        to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
+        return SparseMatrix(r.shape[0], r.shape[1], to(r.data, torch.float64).to(dtype), to(r.indptr, torch.int64),
+                            to(r.indices, torch.int32), to(cc.data, torch.float64).to(dtype),
+                            to(cc.indptr, torch.int64), to(cc.indices, torch.int32))
+
+
+@dataclass
 class Problem:
-    A: Matrix
+    A: object             # Matrix or SparseMatrix
     b: object
     c: object
 
@@ -146,7 +185,10 @@ class Problem:
     def from_lp(lp, dtype=None, device: int = 0) -> "Problem":
         torch = _torch()
         dev = f"cuda:{device}"
-        A = Matrix.from_numpy(lp.A, dtype=dtype, device=device)
+        if hasattr(lp.A, "tocsr"):
+            A = SparseMatrix.from_scipy(lp.A, dtype=dtype, device=device)
+        else:
+            A = Matrix.from_numpy(lp.A, dtype=dtype, device=device)
         b = torch.from_numpy(lp.b).to(dev)
         c = torch.from_numpy(lp.c).to(dev)
         return Problem(A, b, c)

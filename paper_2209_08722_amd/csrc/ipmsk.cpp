@@ -22,7 +22,7 @@ namespace {
 enum WsId {
     W_PART = 0, W_COLPART, W_RED, W_D2, W_RD, W_DS, W_DX, W_RP, W_P, W_DY, W_RHAT, W_G1, W_G2, W_U, W_B,
     W_L, W_X, W_XT, W_T, W_SCAL, W_PCG_VEC, W_PCG_RHO, W_PCG_CD, W_PCG_CI, W_STATUS, W_PART3, W_PARTMIN,
-    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_MLPF, W_MLPD, W_MLPI, W_WQ, W_COUNT
+    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_MLPF, W_MLPD, W_MLPI, W_WQ, W_COEF, W_COUNT
 };
 
 struct TimedPair {
@@ -163,14 +163,22 @@ int elem_size(int dtype) { return dtype == IPM_F64 ? 8 : (dtype == IPM_F32 ? 4 :
 
 int check_matrix(ipm_ctx* ctx, const ipm_matrix* A) {
     if (!A) return fail(ctx, IPM_ERR_ARG, "A is null");
-    if (A->layout != IPM_DENSE_ROWMAJOR) return fail(ctx, IPM_ERR_ARG, "unsupported layout %d", A->layout);
+    if (A->layout != IPM_DENSE_ROWMAJOR && A->layout != IPM_CSR)
+        return fail(ctx, IPM_ERR_ARG, "unsupported layout %d", A->layout);
     const int es = elem_size(A->dtype);
     if (!es) return fail(ctx, IPM_ERR_ARG, "unsupported dtype %d", A->dtype);
     if (A->m < 1 || A->n < 1 || A->m > A->n) return fail(ctx, IPM_ERR_ARG, "need 1 <= m <= n (m=%lld n=%lld)",
                                                           (long long)A->m, (long long)A->n);
     if (A->m > 1 << 20) return fail(ctx, IPM_ERR_ARG, "m too large");
-    if (A->ld < A->n) return fail(ctx, IPM_ERR_ARG, "ld < n");
     if (!A->val) return fail(ctx, IPM_ERR_ARG, "A->val is null");
+    if (A->layout == IPM_CSR) {
+        if (A->n >= ((int64_t)1 << 31)) return fail(ctx, IPM_ERR_ARG, "n too large for 32-bit column indices");
+        if (A->nnz < 0) return fail(ctx, IPM_ERR_ARG, "nnz < 0");
+        if (!A->row_ptr || !A->col_idx || !A->csc_val || !A->col_ptr || !A->row_idx)
+            return fail(ctx, IPM_ERR_ARG, "CSR A needs row_ptr, col_idx and the CSC mirror (csc_val, col_ptr, row_idx)");
+        return IPM_OK;
+    }
+    if (A->ld < A->n) return fail(ctx, IPM_ERR_ARG, "ld < n");
     if ((A->ld * es) % 16 != 0) return fail(ctx, IPM_ERR_ARG, "ld*elem_size must be a multiple of 16 bytes");
     if (reinterpret_cast<uintptr_t>(A->val) % 16 != 0) return fail(ctx, IPM_ERR_ARG, "A->val must be 16-byte aligned");
     return IPM_OK;
@@ -189,6 +197,13 @@ HashKeys make_keys(uint64_t seed, int64_t k, int w, int s) {
 int do_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* dvals, int is_d2, const HashKeys& hk, int w,
               int out_f64, void* B) {
     const int m = (int)A->m;
+    if (A->layout == IPM_CSR) {
+        Timer t(ctx, IPM_KERNEL_SKETCH);
+        HIPCHK(launch_sketch_csr(A->dtype, A->val, A->row_ptr, A->col_idx, m, dvals, is_d2, hk, w, out_f64, B,
+                                 ctx->stream));
+        t.stop();
+        return IPM_OK;
+    }
     const SketchPlan sp = sketch_plan(m, A->n, w, out_f64, ctx->num_cu);
     if (sp.atomic) {
         if (out_f64) {
@@ -284,61 +299,69 @@ int do_factor(ipm_ctx* ctx, int m, int w, int b_f64, const void* B, double* Lw, 
     return IPM_OK;
 }
 
-// Workspace of a strip pass with `nacc` row accumulators (per-block partials and sums).
-int strip_buffers(ipm_ctx* ctx, const StripPlan& pl, int m, int nacc, StripCall* c) {
-    CHK(ws(ctx, W_PART, (size_t)nacc * pl.grid * m, &c->part));
-    CHK(ws(ctx, W_COLPART, (size_t)pl.grid, &c->colpart));
-    CHK(ws(ctx, W_GPART, (size_t)rowsum_blocks(m), &c->gpart));
+// One pass over A for the StripCall c (kind, post step and vectors set by the caller): the dense
+// strip pass and its row reduction, or the two sparse passes. Returns IPM_ERR_ARG if m is too
+// large for the dense pass.
+int run_pass(ipm_ctx* ctx, const ipm_matrix* A, StripCall& c, int kernel_id, int tag) {
+    c.dtype = A->dtype;
+    c.A = A->val;
+    c.m = (int)A->m;
+    c.n = A->n;
+    c.ld = A->ld;
+    const int nacc = c.kind == STRIP_RESID ? 2 : 1;
+    CHK(ws(ctx, W_GPART, (size_t)rowsum_blocks(c.m), &c.gpart));
+    if (A->layout == IPM_CSR) {
+        c.row_ptr = A->row_ptr;
+        c.col_idx = A->col_idx;
+        c.csc_val = A->csc_val;
+        c.col_ptr = A->col_ptr;
+        c.row_idx = A->row_idx;
+        CHK(ws(ctx, W_COEF, (size_t)nacc * (size_t)A->n, &c.coefs));
+        CHK(ws(ctx, W_COLPART, (size_t)sparse_col_blocks(A->n), &c.colpart));
+        HIPCHK(launch_sparse_pass(c, ctx->stream));
+        return IPM_OK;
+    }
+    const StripPlan pl = strip_plan(A->dtype, c.m, A->n, ctx->num_cu, c.kind);
+    if (pl.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", c.m);
+    CHK(ws(ctx, W_PART, (size_t)nacc * pl.grid * c.m, &c.part));
+    CHK(ws(ctx, W_COLPART, (size_t)pl.grid, &c.colpart));
+    if (kernel_id >= 0) {
+        Timer t(ctx, kernel_id, tag);
+        HIPCHK(launch_strip_pass(c, pl, ctx->stream));
+        t.stop();
+    } else {
+        HIPCHK(launch_strip_pass(c, pl, ctx->stream));
+    }
+    HIPCHK(launch_strip_rowsum(c, pl, ctx->stream));
     return IPM_OK;
 }
 
 // One matvec pass over A: out <- A diag(d2) A^T v, accumulated in FP64 (acc64) or FP32.
-int matvec_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v, double* out,
-                const StripPlan& pl, const int* done, int tag, int acc64 = 1) {
+int matvec_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v, double* out, const int* done,
+                int tag, int acc64 = 1) {
     StripCall c{};
     c.kind = STRIP_MATVEC;
-    c.dtype = A->dtype;
     c.acc64 = acc64;
     c.post = POST_PLAIN;
-    c.A = A->val;
-    c.m = (int)A->m;
-    c.n = A->n;
-    c.ld = A->ld;
     c.vec0 = v;
     c.d2 = d2;
     c.out0 = out;
     c.done = done;
-    CHK(strip_buffers(ctx, pl, c.m, 1, &c));
-    Timer t(ctx, acc64 || A->dtype == IPM_F64 ? IPM_KERNEL_MATVEC : IPM_KERNEL_MATVEC32, tag);
-    HIPCHK(launch_strip_pass(c, pl, ctx->stream));
-    t.stop();
-    HIPCHK(launch_strip_rowsum(c, pl, ctx->stream));
-    return IPM_OK;
+    return run_pass(ctx, A, c, acc64 || A->dtype == IPM_F64 ? IPM_KERNEL_MATVEC : IPM_KERNEL_MATVEC32, tag);
 }
 
 // r <- p - A diag(d2) A^T dy with FP64 accumulation whatever the storage type of A (the true
 // residual of the refinement rounds).
-int resid_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* dy, const double* p, double* r,
-               const StripPlan& pl) {
+int resid_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* dy, const double* p, double* r) {
     StripCall c{};
     c.kind = STRIP_MATVEC;
-    c.dtype = A->dtype;
     c.acc64 = 1;
     c.post = POST_RESP;
-    c.A = A->val;
-    c.m = (int)A->m;
-    c.n = A->n;
-    c.ld = A->ld;
     c.vec0 = dy;
     c.d2 = d2;
     c.pvec = p;
     c.out0 = r;
-    CHK(strip_buffers(ctx, pl, c.m, 1, &c));
-    Timer t(ctx, IPM_KERNEL_RESID64);
-    HIPCHK(launch_strip_pass(c, pl, ctx->stream));
-    t.stop();
-    HIPCHK(launch_strip_rowsum(c, pl, ctx->stream));
-    return IPM_OK;
+    return run_pass(ctx, A, c, IPM_KERNEL_RESID64, -1);
 }
 
 struct PcgOut {
@@ -357,14 +380,14 @@ struct PcgCfg {
 // Initial iterate from ncand (1 or 2) candidate vectors cand[0:m], cand[m:2m]: their
 // M-norm-optimal combination into dy_out, M dy_out into q_out and, if r_out is given,
 // p - M dy_out into r_out. The matvecs accumulate in FP64 when acc64 is set.
-int warm_combination(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const StripPlan& pl, const double* p,
-                     const double* cand, int ncand, int acc64, double* dy_out, double* q_out, double* r_out) {
+int warm_combination(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* p, const double* cand,
+                     int ncand, int acc64, double* dy_out, double* q_out, double* r_out) {
     const int m = (int)A->m;
     double* q2 = nullptr;
-    CHK(matvec_pass(ctx, A, d2, cand, q_out, pl, nullptr, -1, acc64));
+    CHK(matvec_pass(ctx, A, d2, cand, q_out, nullptr, -1, acc64));
     if (ncand > 1) {
         CHK(ws(ctx, W_WQ, (size_t)m, &q2));
-        CHK(matvec_pass(ctx, A, d2, cand + m, q2, pl, nullptr, -1, acc64));
+        CHK(matvec_pass(ctx, A, d2, cand + m, q2, nullptr, -1, acc64));
     }
     HIPCHK(launch_warm_galerkin(m, ncand, cand, ncand > 1 ? cand + m : nullptr, p, q_out, q2, dy_out, q_out, r_out,
                                 ctx->stream));
@@ -382,8 +405,6 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     double* XT = nullptr;
     CHK(ws(ctx, W_XT, (size_t)m * m, &XT));
     if (!cfg.xt_ready) HIPCHK(launch_transpose(X, XT, m, st));
-    const StripPlan pl = strip_plan(A->dtype, m, A->n, ctx->num_cu, STRIP_MATVEC);
-    if (pl.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
     double *vec = nullptr, *rho = nullptr, *cd = nullptr, *info = nullptr;
     int* ci = nullptr;
     CHK(ws(ctx, W_PCG_VEC, (size_t)8 * m, &vec));
@@ -414,7 +435,7 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     b.stag_window = prm->stag_window;
     b.maxit = cfg.maxit;
     HIPCHK(launch_fill_i32(ci, PI_COUNT, 0, st));
-    if (warm) CHK(warm_combination(ctx, A, d2, pl, p, cand, ncand, cfg.acc64, dy_out, b.q, nullptr));
+    if (warm) CHK(warm_combination(ctx, A, d2, p, cand, ncand, cfg.acc64, dy_out, b.q, nullptr));
     HIPCHK(launch_pcg_init1(b, warm, st));
     HIPCHK(launch_pcg_init2(b, warm, dy_out, st));
     int* hi = reinterpret_cast<int*>(ctx->pinned);
@@ -425,7 +446,7 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     const int* done = ci + PI_DONE;
     for (;;) {
         for (int t = 0; t < batch && j < cfg.maxit; ++t, ++j) {
-            CHK(matvec_pass(ctx, A, d2, b.dv, b.q, pl, done, j, cfg.acc64));
+            CHK(matvec_pass(ctx, A, d2, b.dv, b.q, done, j, cfg.acc64));
             HIPCHK(launch_pcg_gemv1(b, j, st));
             HIPCHK(launch_pcg_gemv2(b, j, st));
         }
@@ -468,8 +489,6 @@ int do_pcg_mixed(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const doub
                  double* dy, const double* cand, int ncand, const ipm_params* prm, PcgOut* out) {
     hipStream_t st = ctx->stream;
     const int m = (int)A->m;
-    const StripPlan pl = strip_plan(A->dtype, m, A->n, ctx->num_cu, STRIP_MATVEC);
-    if (pl.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
     double *ref = nullptr, *XT = nullptr;
     CHK(ws(ctx, W_REF, (size_t)4 * m + 8, &ref));
     CHK(ws(ctx, W_XT, (size_t)m * m, &XT));
@@ -484,7 +503,7 @@ int do_pcg_mixed(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const doub
     out->warm_used = 0;
     if (ncand > 0) {
         // M-norm-optimal combination of the candidates and its residual, FP64 accumulation
-        CHK(warm_combination(ctx, A, d2, pl, p, cand, ncand, 1, dyw, delta, r));
+        CHK(warm_combination(ctx, A, d2, p, cand, ncand, 1, dyw, delta, r));
         CHK(precond_norm2(ctx, X, m, r, g, sc + 2));
         HIPCHK(hipMemcpyAsync(hd, sc, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -543,7 +562,7 @@ int do_pcg_mixed(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const doub
             continue;
         }
         HIPCHK(launch_axpy(m, 1.0, delta, dy, st));
-        CHK(resid_pass(ctx, A, d2, dy, p, r, pl));
+        CHK(resid_pass(ctx, A, d2, dy, p, r));
     }
     out->iters = total;
     out->rounds = rounds;
@@ -751,10 +770,7 @@ int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const
     CHK(check_matrix(ctx, A));
     if (!d2 || !v || !q) return fail(ctx, IPM_ERR_ARG, "null pointer");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
-    const int m = (int)A->m;
-    const StripPlan pl = strip_plan(A->dtype, m, A->n, ctx->num_cu, STRIP_MATVEC);
-    if (pl.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
-    CHK(matvec_pass(ctx, A, d2, v, q, pl, nullptr, -1));
+    CHK(matvec_pass(ctx, A, d2, v, q, nullptr, -1));
     return IPM_OK;
 }
 
@@ -795,8 +811,6 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
     CHK(ws(ctx, W_SCAL, SC_COUNT, &scal));
     CHK(ws(ctx, W_PART3, (size_t)3 * Gn, &part3));
     CHK(ws(ctx, W_PARTMIN, Gn, &partmin));
-    const StripPlan plr = strip_plan(IPM_F64 == A->dtype ? IPM_F64 : A->dtype, m, n, ctx->num_cu, STRIP_RESID);
-    if (plr.nt <= 0) return fail(ctx, IPM_ERR_ARG, "m=%d too large for the dense pass", m);
     CHK(ws(ctx, W_SQ, 4, &sq));
 
     // residuals, mu, p and the stop test at the current point (Algorithm 3, step 3)
@@ -805,12 +819,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
     {
         StripCall c{};
         c.kind = STRIP_RESID;
-        c.dtype = A->dtype;
         c.acc64 = 1;
-        c.A = A->val;
-        c.m = m;
-        c.n = n;
-        c.ld = A->ld;
         c.vec0 = state->y;
         c.d2 = d2;
         c.x = state->x;
@@ -823,8 +832,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         c.out0 = rp;
         c.out1 = p;
         c.outsc = sq;
-        CHK(strip_buffers(ctx, plr, m, 2, &c));
-        HIPCHK(launch_strip(c, plr, st));
+        CHK(run_pass(ctx, A, c, -1, -1));
     }
     const int set_ref = state->r0norm < 0.0 ? 1 : 0;
     HIPCHK(launch_metrics(n, m, ctx->ws[W_GPART] ? reinterpret_cast<double*>(ctx->ws[W_GPART]) : nullptr,
@@ -922,15 +930,9 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
 
     // directions (eq. ipm_inf): ds, true residual, v, dx
     {
-        const StripPlan pld = strip_plan(A->dtype, m, n, ctx->num_cu, STRIP_DIR);
         StripCall c{};
         c.kind = STRIP_DIR;
-        c.dtype = A->dtype;
         c.acc64 = 1;
-        c.A = A->val;
-        c.m = m;
-        c.n = n;
-        c.ld = A->ld;
         c.vec0 = dyv;
         c.d2 = d2;
         c.rd = rd;
@@ -938,8 +940,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         c.post = POST_RHAT;
         c.pvec = p;
         c.out0 = rhat;
-        CHK(strip_buffers(ctx, pld, m, 1, &c));
-        HIPCHK(launch_strip(c, pld, st));
+        CHK(run_pass(ctx, A, c, -1, -1));
     }
     double* u = nullptr;
     CHK(ws(ctx, W_U, (size_t)wmax, &u));

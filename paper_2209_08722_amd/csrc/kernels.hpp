@@ -59,6 +59,13 @@ struct StripCall {
     double* colpart;         // [grid] per-block column reductions (resid: sum of r_d^2)
     double* gpart;           // resid post: per-reduction-block sums of r_p^2 [rowsum_blocks(m)]
     const int* done;         // early-exit flag (may be null)
+    // sparse A (CSR with a CSC mirror of the same nonzeros); A above is the CSR values
+    const int64_t* row_ptr;  // m + 1
+    const int32_t* col_idx;  // nnz
+    const void* csc_val;     // nnz, column order
+    const int64_t* col_ptr;  // n + 1
+    const int32_t* row_idx;  // nnz
+    double* coefs;           // [nacc][n] column coefficients between the two sparse passes
 };
 
 StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind);
@@ -67,6 +74,18 @@ hipError_t launch_strip_pass(const StripCall& c, const StripPlan& p, hipStream_t
 hipError_t launch_strip_rowsum(const StripCall& c, const StripPlan& p, hipStream_t st);
 int rowsum_blocks(int m);
 constexpr int kStripMaxGrid = 4096;
+
+// ---- sparse A (sparse.hip) ----
+// The same passes for CSR A: a column pass over the CSC mirror (column dots, per-column step,
+// coefficients into c.coefs, column reductions into c.colpart[sparse_col_blocks(n)]) and a row
+// pass over CSR (row sums with the coefficients and the RowPost step, one wave per row, with the
+// reduction-block layout of launch_strip_rowsum).
+int sparse_col_blocks(int64_t n);
+hipError_t launch_sparse_pass(const StripCall& c, hipStream_t st);
+// B = A D W for CSR A: one block per (row, bucket range of one copy), LDS buckets in FP64.
+hipError_t launch_sketch_csr(int dtype, const void* val, const int64_t* row_ptr, const int32_t* col_idx, int m,
+                             const double* dvals, int dvals_are_d2, const HashKeys& hk, int w, int out_f64, void* B,
+                             hipStream_t st);
 
 // ---- sketch and perturbation -----------------------------------------------------------------
 struct SketchPlan { int rows_per_block; int chunks; int64_t cols_per_chunk; size_t lds; bool atomic; bool global_only; int range_width; };

@@ -19,7 +19,7 @@
 // The CG matvec q = A D^2 A^T v (Algorithm 1, step 3) is one such pass; so are the residual
 // pass (r_d = A^T y + s - c, then A x and A u for r_p and p, Section 5 / Algorithm 3 step 3) and
 // the direction pass (ds = -r_d - A^T dy, then A D^2 A^T dy for the true residual).
-#include "kernels.hpp"
+#include "strip_ops.hpp"
 
 namespace ipmsk {
 
@@ -28,53 +28,6 @@ namespace {
 constexpr int kLpr = 8;      // lanes per row segment (8 x 16 B = 128 B)
 constexpr int kRrNt = 512;   // re-read form: threads per block
 constexpr int kRrCh = 4;     // re-read form: rows per thread per chunk
-
-struct OpMatvec {
-    static constexpr int NACC = 1, NCR = 0;
-    static constexpr bool PF = true;
-    struct S {};
-    __device__ static S init(const StripCall&) { return {}; }
-    __device__ static double pre(const StripCall& a, int64_t j, bool valid) { return valid ? a.d2[j] : 0.0; }
-    template <typename ACC>
-    __device__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool, ACC dot, ACC* coef,
-                                  double*, double pf) {
-        coef[0] = valid ? (ACC)pf * dot : (ACC)0;
-    }
-};
-
-struct OpResid {
-    static constexpr bool PF = false;
-    __device__ static double pre(const StripCall&, int64_t, bool) { return 0.0; }
-    static constexpr int NACC = 2, NCR = 1;
-    struct S { double smu; };
-    __device__ static S init(const StripCall& a) { return S{a.scal[SC_SMU]}; }
-    template <typename ACC>
-    __device__ static void column(const StripCall& a, const S& st, int64_t j, bool valid, bool writer, ACC dot,
-                                  ACC* coef, double* cr, double) {
-        if (!valid) { coef[0] = coef[1] = (ACC)0; return; }
-        const double sj = a.s[j];
-        const double rdj = (double)dot + sj - a.c[j];
-        if (writer) { a.rd_out[j] = rdj; cr[0] += rdj * rdj; }
-        coef[0] = (ACC)a.x[j];
-        coef[1] = (ACC)(st.smu / sj + a.d2[j] * rdj);
-    }
-};
-
-struct OpDir {
-    static constexpr bool PF = false;
-    __device__ static double pre(const StripCall&, int64_t, bool) { return 0.0; }
-    static constexpr int NACC = 1, NCR = 0;
-    struct S {};
-    __device__ static S init(const StripCall&) { return {}; }
-    template <typename ACC>
-    __device__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool writer, ACC dot,
-                                  ACC* coef, double*, double) {
-        if (!valid) { coef[0] = (ACC)0; return; }
-        const double t = (double)dot;
-        if (writer) a.ds_out[j] = -a.rd[j] - t;
-        coef[0] = (ACC)(a.d2[j] * t);
-    }
-};
 
 // Sum of the per-block partials part[acc][row][block] and the RowPost step: one wave per row.
 constexpr int RNT = 256;

@@ -26,7 +26,7 @@ IPM_ERR_STALL = -5
 IPM_ERR_NOMEM = -6
 
 IPM_F64, IPM_F32, IPM_BF16 = 0, 1, 2
-IPM_DENSE_ROWMAJOR = 0
+IPM_DENSE_ROWMAJOR, IPM_CSR = 0, 1
 IPM_KERNEL_MATVEC, IPM_KERNEL_SKETCH, IPM_KERNEL_GRAM, IPM_KERNEL_MATVEC32, IPM_KERNEL_RESID64 = 0, 1, 2, 3, 4
 IPM_PLAIN, IPM_MIXED, IPM_MIXED_F32ACC = 0, 1, 2
 IPM_WARM_NONE, IPM_WARM_PREV, IPM_WARM_GIVEN = 0, 1, 2
@@ -41,7 +41,8 @@ STATUS_NAMES = {
 
 class IpmMatrix(ctypes.Structure):
     _fields_ = [("m", c_int64), ("n", c_int64), ("ld", c_int64), ("layout", c_int32),
-                ("dtype", c_int32), ("val", c_void_p)]
+                ("dtype", c_int32), ("val", c_void_p), ("nnz", c_int64), ("row_ptr", c_void_p),
+                ("col_idx", c_void_p), ("csc_val", c_void_p), ("col_ptr", c_void_p), ("row_idx", c_void_p)]
 
 
 class IpmProblem(ctypes.Structure):
