@@ -40,16 +40,26 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def traffic_record(kernel_src: str, workload: str):
+MATVEC_SOURCES = ("strip.hip", "strip_ops.hpp", "common.hpp")
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the sources that define the CG matvec kernel."""
+    h = hashlib.sha256()
+    for name in MATVEC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2209_08722_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_record(workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
-    kernel source changed since the counters were taken."""
+    kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "matvec_traffic.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
-        src = open(kernel_src, "rb").read()
-        if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        if rec.get("source_sha256") != kernel_source_hash():
             return None
         return rec.get("per_launch_bytes", {}).get(workload)
     except Exception:
@@ -301,7 +311,7 @@ def main() -> int:
     mv_gbs = mv_bytes / mv_avg / 1e9 if mv_n else None
     sk_gbs = sk_bytes / (sk_ms / max(sk_n, 1) * 1e-3) / 1e9 if sk_n else None
     gr_tf = gram_flops / (gr_ms / max(gr_n, 1) * 1e-3) / 1e12 if gr_n else None
-    traffic = traffic_record(os.path.join(ROOT, "paper_2209_08722_amd", "csrc", "strip.hip"), args.workload)
+    traffic = traffic_record(args.workload)
 
     out = {
         "metric": "IPM iter/s + matvec HBM GB/s, FP64 plain vs mixed+learned at gap 1e-8",

@@ -105,67 +105,65 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 
 // Factor the kb x kb diagonal block at (k0, k0) of the partially updated matrix in place
 // (lower triangle) and write its inverse into X's diagonal block (zero above the diagonal).
-// One wave, no LDS. Lane t keeps row t of the block in registers; step c of the right-looking
-// factorization reads l_jc from lane j's register with readlane (compile-time lane index) and
-// updates every j > c (for j > t that only touches the unused upper part of the row, which
-// keeps the unrolled code free of predication). The inverse's column t comes from forward
-// substitution X L = I, reading row i of L from lane i the same way, with four independent
-// accumulators. A pivot that is not positive is recorded in *status (smallest index wins) and
-// replaced by 1 so the remaining work stays finite.
-__global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ Lw, int64_t ld, int k0, int kb,
-                                                   double* __restrict__ X, int64_t ldx, int* __restrict__ status) {
-    const int t = threadIdx.x;
-    double r[64];
-    const double* src = Lw + (int64_t)(k0 + (t < kb ? t : 0)) * ld + k0;
+// Two waves. The block is loaded with coalesced row reads into LDS and padded to 64 x 64 with the
+// identity (the factor and inverse of diag(A, I) are diag(L, I) and diag(L^-1, I)), so no step
+// below tests bounds. Wave 0, lane t, keeps row t of the matrix in registers: step c of the
+// right-looking factorization takes the pivot from lane c, scales column c, publishes it in LDS
+// (entry c is l_cc) and updates the row with uniform-address (broadcast) reads of that column; for
+// j > t the update only touches the unused upper part. Wave 1, lane t, keeps column t of the
+// inverse and does step c of the column-oriented forward substitution L x = e_t with the same
+// published column (x_c = y_c / l_cc, then y_i -= l_ic x_c for i > c), storing X's row c
+// (coalesced). L goes back through LDS for a coalesced write. A pivot that is not positive is
+// recorded in *status (smallest index wins) and replaced by 1 so the remaining work stays finite.
+__global__ __launch_bounds__(128) void k_potrf_diag(double* __restrict__ Lw, int64_t ld, int k0, int kb,
+                                                    double* __restrict__ X, int64_t ldx, int* __restrict__ status) {
+    __shared__ double col[2][64];
+    __shared__ double Ls[64][65];
+    const int lane = threadIdx.x & 63;
+    const bool fac = threadIdx.x < 64;   // wave 0 factors, wave 1 inverts
+    for (int i = threadIdx.x >> 6; i < 64; i += 2) {
+        double v = (i == lane) ? 1.0 : 0.0;
+        if (i < kb && lane < kb && lane <= i) v = Lw[(int64_t)(k0 + i) * ld + k0 + lane];
+        Ls[i][lane] = v;
+    }
+    __syncthreads();
+    double z[64];   // wave 0: row `lane` of the matrix; wave 1: column `lane` of the inverse
 #pragma unroll
-    for (int j = 0; j < 64; ++j) r[j] = (t < kb && j <= t) ? src[j] : 0.0;
+    for (int j = 0; j < 64; ++j) z[j] = fac ? Ls[lane][j] : ((j == lane) ? 1.0 : 0.0);
+    double* xcol = X + (int64_t)k0 * ldx + k0 + lane;
+    const bool xw = !fac && lane < kb;
+    int bad = INT_MAX;
 #pragma unroll
     for (int c = 0; c < 64; ++c) {
-        if (c < kb) {
-            double piv = readlane_d(r[c], c);
+        double* cc = col[c & 1];
+        if (fac) {
+            double piv = readlane_d(z[c], c);
             if (!(piv > 0.0)) {
-                if (t == 0) atomicMin(status, k0 + c);
+                bad = min(bad, k0 + c);
                 piv = 1.0;
             }
             const double lcc = sqrt(piv);
-            const double inv = 1.0 / lcc;
-            r[c] = (t == c) ? lcc : r[c] * inv;
-            const double ltc = r[c];
-#pragma unroll
-            for (int j = c + 1; j < 64; ++j) r[j] = fma(-ltc, readlane_d(r[c], j), r[j]);
+            z[c] = (lane == c) ? lcc : z[c] * (1.0 / lcc);
+            cc[lane] = z[c];
+            Ls[lane][c] = z[c];            // L[lane][c], final
         }
-    }
-    if (t < kb) {
-        double* dst = Lw + (int64_t)(k0 + t) * ld + k0;
+        __syncthreads();
+        if (fac) {
+            const double ltc = z[c];
 #pragma unroll
-        for (int j = 0; j < 64; ++j)
-            if (j <= t) dst[j] = r[j];
-    }
-    // column t of X = L^{-1}: X[i][t] = (delta_it - sum_{q<i} L[i][q] X[q][t]) / L[i][i]
-    double x[64];
-#pragma unroll
-    for (int i = 0; i < 64; ++i) {
-        if (i < kb) {
-            double s0 = (i == t) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-            for (int q = 0; q + 3 < i; q += 4) {
-                s0 = fma(-readlane_d(r[q], i), x[q], s0);
-                s1 = fma(-readlane_d(r[q + 1], i), x[q + 1], s1);
-                s2 = fma(-readlane_d(r[q + 2], i), x[q + 2], s2);
-                s3 = fma(-readlane_d(r[q + 3], i), x[q + 3], s3);
-            }
-#pragma unroll
-            for (int q = i & ~3; q < i; ++q) s0 = fma(-readlane_d(r[q], i), x[q], s0);
-            x[i] = ((s0 + s1) + (s2 + s3)) / readlane_d(r[i], i);
+            for (int j = c + 1; j < 64; ++j) z[j] = fma(-ltc, cc[j], z[j]);
         } else {
-            x[i] = 0.0;
+            z[c] = z[c] / cc[c];           // X[c][lane], final
+            if (xw && c < kb) xcol[(int64_t)c * ldx] = z[c];
+            const double xc = z[c];
+#pragma unroll
+            for (int j = c + 1; j < 64; ++j) z[j] = fma(-cc[j], xc, z[j]);
         }
     }
-    if (t < kb) {
-#pragma unroll
-        for (int i = 0; i < 64; ++i)
-            if (i < kb) X[(int64_t)(k0 + i) * ldx + k0 + t] = x[i];
-    }
+    if (fac && lane == 0 && bad != INT_MAX) atomicMin(status, bad);
+    __syncthreads();
+    for (int i = threadIdx.x >> 6; i < kb; i += 2)
+        if (lane <= i) Lw[(int64_t)(k0 + i) * ld + k0 + lane] = Ls[i][lane];
 }
 
 __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ X, double* __restrict__ XT, int m) {
@@ -242,7 +240,7 @@ hipError_t launch_sgram_f32(int m, int w, const float* B, double* C, int ksplit,
 hipError_t launch_potrf_diag(double* Lw, int64_t ld, int k0, int kb, double* X, int64_t ldx, int* status,
                              hipStream_t st) {
     if (kb < 1 || kb > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, st, Lw, ld, k0, kb, X, ldx, status);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(128), 0, st, Lw, ld, k0, kb, X, ldx, status);
     return hipGetLastError();
 }
 

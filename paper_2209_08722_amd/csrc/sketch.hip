@@ -44,7 +44,7 @@ __global__ __launch_bounds__(SNT) void k_sketch_lds(const T* __restrict__ A, int
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 const int i = row0 + rr;
-                av[u][rr] = (ok && i < m) ? (double)Elem<T>::load1(A + (int64_t)i * ld + j) : 0.0;
+                av[u][rr] = (ok && i < m) ? (double)Elem<T>::load1_stream(A + (int64_t)i * ld + j) : 0.0;
             }
         }
 #pragma unroll
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(SNT) void k_sketch_range(const T* __restrict__ A, i
             const bool ok = j < n;
             const double dd = ok ? dv[j] : 0.0;
             dj[u] = d_is_d2 ? sqrt(dd) : dd;
-            av[u] = ok ? (double)Elem<T>::load1(row + j) : 0.0;
+            av[u] = ok ? (double)Elem<T>::load1_stream(row + j) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < SUNROLL; ++u) {

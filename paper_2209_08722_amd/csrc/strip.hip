@@ -132,7 +132,7 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
         for (int k = 0; k < RPT; ++k) {
             const int i = g + RG * k;
             const T* ptr = A + (int64_t)strip * SW + (int64_t)(RG * k) * a.ld + lane_off;
-            if (i < m && left >= VEC) av[k] = Elem<T>::raw16(ptr);
+            if (i < m && left >= VEC) av[k] = raw16_stream(ptr);
             else if (i < m && left > 0) av[k] = raw_partial<T>(ptr, (int)left);
             else av[k] = make_uint4(0u, 0u, 0u, 0u);
         }
