@@ -61,7 +61,8 @@ typedef struct ipm_ctx ipm_ctx;
 
 /* Constraint matrix A (m x n).
  * IPM_DENSE_ROWMAJOR: val [device] m*ld elements of `dtype`; the sparse fields are ignored.
- * IPM_CSR (the sparse LPs of Section 6): the nnz nonzeros twice, all [device]:
+ * IPM_CSR (A by its nonzeros; the method's cost is stated in nnz(A), Section 3 and the running
+ *   time discussion of Section 4): the nnz nonzeros twice, all [device]:
  *   row order    val (nnz of `dtype`), row_ptr (m+1, int64), col_idx (nnz, int32, < n);
  *   column order csc_val (nnz of `dtype`), col_ptr (n+1, int64), row_idx (nnz, int32, < m);
  *   both orders hold the same values. ld is ignored and n must be below 2^31. The index arrays

@@ -152,18 +152,19 @@ CONFIGS = {
     2: dict(m=1000, n=1_000_000, storage="bf16", w=4000, s=2, seeds=[0], density=1e-3),
     3: dict(m=2000, n=200_000, storage="f32", w=8000, s=2, seeds=list(range(80))),
     "4d": dict(m=2000, n=2_000_000, storage="bf16", w=16000, s=2, seeds=[0]),
+    "4s": dict(m=5000, n=2_000_000, storage="bf16", w=40000, s=2, seeds=[0], density=5e-4),
 }
 
 
 def config(i, seed: Optional[int] = None) -> LP:
-    """Build workload ``i`` (0, 1, 2, 3 or "4d") at ``seed`` (defaults to its first seed)."""
+    """Build workload ``i`` (0, 1, 2, 3, "4d" or "4s") at ``seed`` (defaults to its first seed)."""
     cfg = CONFIGS[i]
     sd = cfg["seeds"][0] if seed is None else seed
     if i == 3:
         lp = illcond_lp(cfg["m"], cfg["n"], seed=sd, storage=cfg["storage"])
-    elif i == 2:
+    elif "density" in cfg:
         lp = sparse_lp(cfg["m"], cfg["n"], cfg["density"], seed=sd, storage=cfg["storage"],
-                       name=f"cfg2s{sd}")
+                       name=f"cfg{i}s{sd}")
     else:
         lp = dense_lp(cfg["m"], cfg["n"], seed=sd, storage=cfg["storage"],
                       name=f"cfg{i}s{sd}")

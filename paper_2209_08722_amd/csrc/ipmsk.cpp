@@ -220,23 +220,94 @@ int do_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* dvals, int is_d2,
 
 // Q = B B^T (lower) plus delta I, Q = L L^T in place in Lw, X = L^{-1}. *bad receives the
 // first bad pivot or -1 and *trace the trace of B B^T.
+// C = alpha A B (no transposes; C overwritten): the 128-tile kernel when it has work for half the
+// CUs, else the 64-tile kernel, with split-K (C cleared first) when the tiles alone cannot fill
+// the chip and `split` allows it.
+int gemm_nn(ipm_ctx* ctx, int M, int N, int K, double alpha, const double* A, int64_t lda, const double* B,
+            int64_t ldb, double* C, int64_t ldc, bool split);
+
+// Rows [64 lo, 64 hi) of the triangular inverse X = L^{-1} (row-major m x m, diagonal 64-blocks
+// already inverted, zero above the diagonal): the 2 x 2 block identity
+// X21 = -X22 (L21 X11), halves inverted first. T: scratch of at least (m/2 + 64)^2 doubles.
+int tri_inverse(ipm_ctx* ctx, int m, const double* L, double* X, double* T, int lo, int hi) {
+    if (hi - lo <= 1) return IPM_OK;
+    const int mid = (lo + hi) / 2;
+    CHK(tri_inverse(ctx, m, L, X, T, lo, mid));
+    CHK(tri_inverse(ctx, m, L, X, T, mid, hi));
+    const int r1 = lo * 64, r2 = mid * 64, r3 = hi * 64 < m ? hi * 64 : m;
+    const int n1 = r2 - r1, n2 = r3 - r2;
+    CHK(gemm_nn(ctx, n2, n1, n1, 1.0, L + (int64_t)r2 * m + r1, m, X + (int64_t)r1 * m + r1, m, T, n1, true));
+    CHK(gemm_nn(ctx, n2, n1, n2, -1.0, X + (int64_t)r2 * m + r2, m, T, n1, X + (int64_t)r2 * m + r1, m, true));
+    return IPM_OK;
+}
+
+// Split-K factor for the 128-tile product: the smallest split (at most 8, chunks of at least 512)
+// that fills the last round of one-block-per-CU waves best.
+int big_ksplit(int tiles, int K, int num_cu) {
+    int best = 1;
+    double best_eff = 0.0;
+    for (int ks = 1; ks <= 8 && (ks == 1 || K / ks >= 512); ++ks) {
+        const int blocks = tiles * ks;
+        const int rounds = (blocks + num_cu - 1) / num_cu;
+        const double eff = (double)blocks / ((double)rounds * num_cu);
+        if (eff > best_eff + 0.02) {
+            best_eff = eff;
+            best = ks;
+        }
+    }
+    return best;
+}
+
+int gemm_nn(ipm_ctx* ctx, int M, int N, int K, double alpha, const double* A, int64_t lda, const double* B,
+            int64_t ldb, double* C, int64_t ldc, bool split) {
+    hipStream_t st = ctx->stream;
+    const int big_tiles = gemm_big_tiles(M, N, false);
+    if (big_tiles >= ctx->num_cu / 2) {
+        const int ks = split ? big_ksplit(big_tiles, K, ctx->num_cu) : 1;
+        if (ks > 1) HIPCHK(launch_fill_2d(C, M, N, ldc, st));
+        HIPCHK(launch_dgemm_big(false, false, M, N, K, alpha, A, lda, B, ldb, 0.0, C, ldc, ks, st));
+        return IPM_OK;
+    }
+    const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    int ks = split ? (2 * ctx->num_cu + tiles - 1) / tiles : 1;
+    const int kmax = (K + 63) / 64;
+    if (ks > kmax) ks = kmax;
+    if (ks < 1) ks = 1;
+    if (ks > 1) HIPCHK(launch_fill_2d(C, M, N, ldc, st));
+    HIPCHK(launch_dgemm(false, false, M, N, K, alpha, A, lda, B, ldb, 0.0, C, ldc, ks, st));
+    return IPM_OK;
+}
+
 int factor_once(ipm_ctx* ctx, int m, int w, int b_f64, const void* B, double* Lw, double* X, double delta,
                 int64_t* bad, double* trace) {
     hipStream_t st = ctx->stream;
-    const int T = (m + 63) / 64;
-    const int tiles = T * (T + 1) / 2;
-    int ksplit = (2 * ctx->num_cu + tiles - 1) / tiles;
-    const int kmax = (w + 63) / 64;
-    if (ksplit > kmax) ksplit = kmax;
-    if (ksplit < 1) ksplit = 1;
+    // Gram Q = B B^T (lower tiles): the 128-tile pipelined kernel once it has work for every CU,
+    // else the 64-tile kernel with split-K
+    const int big_tiles = gemm_big_tiles(m, m, true);
+    const bool big = big_tiles >= ctx->num_cu / 2;
+    int ksplit;
+    if (big) {
+        ksplit = big_ksplit(big_tiles, w, ctx->num_cu);
+    } else {
+        const int T = (m + 63) / 64;
+        const int tiles = T * (T + 1) / 2;
+        ksplit = (2 * ctx->num_cu + tiles - 1) / tiles;
+        const int kmax = (w + 63) / 64;
+        if (ksplit > kmax) ksplit = kmax;
+        if (ksplit < 1) ksplit = 1;
+    }
     if (ksplit > 1) HIPCHK(launch_fill(Lw, (int64_t)m * m, 0.0, st));
     {
         Timer t(ctx, IPM_KERNEL_GRAM);
-        if (b_f64)
-            HIPCHK(launch_dgemm(true, true, m, m, w, 1.0, reinterpret_cast<const double*>(B), w,
-                                reinterpret_cast<const double*>(B), w, 0.0, Lw, m, ksplit, st));
-        else
-            HIPCHK(launch_sgram_f32(m, w, reinterpret_cast<const float*>(B), Lw, ksplit, st));
+        if (b_f64) {
+            const double* Bd = reinterpret_cast<const double*>(B);
+            if (big) HIPCHK(launch_dgemm_big(true, true, m, m, w, 1.0, Bd, w, Bd, w, 0.0, Lw, m, ksplit, st));
+            else HIPCHK(launch_dgemm(true, true, m, m, w, 1.0, Bd, w, Bd, w, 0.0, Lw, m, ksplit, st));
+        } else {
+            const float* Bf = reinterpret_cast<const float*>(B);
+            if (big) HIPCHK(launch_sgram_f32_big(m, w, Bf, Lw, ksplit, st));
+            else HIPCHK(launch_sgram_f32(m, w, Bf, Lw, ksplit, st));
+        }
         t.stop();
     }
     int* status = nullptr;
@@ -254,24 +325,18 @@ int factor_once(ipm_ctx* ctx, int m, int w, int b_f64, const void* B, double* Lw
             double* panel = Lw + (int64_t)(k0 + kb) * m + k0;
             HIPCHK(launch_dgemm(true, false, rem, kb, kb, 1.0, panel, m, X + (int64_t)k0 * m + k0, m, 0.0, panel, m, 1,
                                 st));
-            HIPCHK(launch_dgemm(true, true, rem, rem, kb, -1.0, panel, m, panel, m, 1.0,
-                                Lw + (int64_t)(k0 + kb) * m + (k0 + kb), m, 1, st));
+            double* trail = Lw + (int64_t)(k0 + kb) * m + (k0 + kb);
+            if (gemm_big_tiles(rem, rem, true) >= 2 * ctx->num_cu)
+                HIPCHK(launch_dgemm_big(true, true, rem, rem, kb, -1.0, panel, m, panel, m, 1.0, trail, m, 1, st));
+            else
+                HIPCHK(launch_dgemm(true, true, rem, rem, kb, -1.0, panel, m, panel, m, 1.0, trail, m, 1, st));
         }
     }
-    // X = L^{-1} by block rows: X[r, :r] = -X[r, r] * (L[r, :r] * X[:r, :r])
+    // X = L^{-1} off the diagonal blocks, recursively: X21 = -X22 (L21 X11)
     double* Tm = nullptr;
-    CHK(ws(ctx, W_T, (size_t)64 * m, &Tm));
-    for (int r0 = 64; r0 < m; r0 += 64) {
-        const int rb = (m - r0) < 64 ? (m - r0) : 64;
-        const int ntile = (r0 + 63) / 64;
-        int ks = ctx->num_cu / ntile;
-        if (ks > r0 / 64) ks = r0 / 64;
-        if (ks < 1) ks = 1;
-        if (ks > 1) HIPCHK(launch_fill(Tm, (int64_t)rb * m, 0.0, st));
-        HIPCHK(launch_dgemm(false, false, rb, r0, r0, 1.0, Lw + (int64_t)r0 * m, m, X, m, 0.0, Tm, m, ks, st));
-        HIPCHK(launch_dgemm(false, false, rb, r0, rb, -1.0, X + (int64_t)r0 * m + r0, m, Tm, m, 0.0,
-                            X + (int64_t)r0 * m, m, 1, st));
-    }
+    const int64_t half = (int64_t)(m / 2 + 64);
+    CHK(ws(ctx, W_T, (size_t)(half * half), &Tm));
+    CHK(tri_inverse(ctx, m, Lw, X, Tm, 0, (m + 63) / 64));
     int* hs = reinterpret_cast<int*>(ctx->pinned);
     HIPCHK(hipMemcpyAsync(hs, status, 2 * sizeof(int) + sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

@@ -109,6 +109,13 @@ hipError_t launch_dgemm(bool trans_b, bool lower_only, int M, int N, int K, doub
                         const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                         double* C, int64_t ldc, int ksplit, hipStream_t st);
 hipError_t launch_sgram_f32(int m, int w, const float* B, double* C, int ksplit, hipStream_t st);
+// The same products with 128 x 128 tiles and a pipelined K loop (for large M and N).
+int gemm_big_tiles(int M, int N, bool lower_only);
+hipError_t launch_dgemm_big(bool trans_b, bool lower_only, int M, int N, int K, double alpha, const double* A,
+                            int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int ksplit,
+                            hipStream_t st);
+hipError_t launch_sgram_f32_big(int m, int w, const float* B, double* C, int ksplit, hipStream_t st);
+hipError_t launch_fill_2d(double* C, int M, int N, int64_t ldc, hipStream_t st);   // M x N block of C <- 0
 hipError_t launch_potrf_diag(double* Lw, int64_t ld, int k0, int kb, double* X, int64_t ldx, int* status,
                              hipStream_t st);
 hipError_t launch_transpose(const double* X, double* XT, int m, hipStream_t st);

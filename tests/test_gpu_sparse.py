@@ -1,10 +1,11 @@
-"""Parity of the sparse (CSR) path with the FP64 oracle on seeded sparse LPs (Section 6's sparse
-workloads: uniform random pattern, N(0, 1) values).
+"""Parity of the sparse (CSR) path with the FP64 oracle on seeded sparse LPs (uniform random
+pattern, N(0, 1) values; the method's cost is stated in nnz(A), Sections 3 and 4).
 
 The matvec and the sketch are compared element by element against the oracle's routines with
 FP64 summation bounds; the IPM step in lockstep with the oracle's step on the same scipy matrix;
-solves against the oracle's optimum. The full-size case is the 1000 x 10^6 matrix with density
-10^-3 (BF16 values), solved in the plain form (FP64 copy of the same values) and the mixed form.
+solves against the oracle's optimum. The full-size cases are the 1000 x 10^6 matrix with density
+10^-3 and the 5000 x 2*10^6 matrix with density 5*10^-4 (BF16 values), solved in the plain form
+(FP64 copy of the same values) and the mixed form.
 """
 import numpy as np
 import pytest
@@ -274,3 +275,49 @@ def test_config2_full_size_solves(ctx, lp2):
         obj = _check(lp, res)
         assert abs(obj - opt) <= 1e-7 * (1 + abs(opt))
     print(f"\nplain {plain.iterations} iterations, mixed {mixed.iterations}", flush=True)
+
+
+# ------------------------------------------------------------------------- 5000 x 2e6 (Gram-dominated)
+
+@pytest.fixture(scope="module")
+def lp4s():
+    print("\ngenerating the 5000 x 2e6 sparse LP (density 5e-4, BF16 values)", flush=True)
+    return lpgen.config("4s")
+
+
+def test_config4s_full_size_matvec_and_sketch(ctx, lp4s):
+    lp = lp4s
+    m, n = lp.A.shape
+    rng = np.random.default_rng(9)
+    d = np.exp(rng.uniform(-3, 3, n))
+    M = _smat(lp.A, "bf16")
+    v = rng.standard_normal(m)
+    q = host(P.ipm_normal_matvec(ctx, M, dev(d * d), dev(v)))
+    ref = oipm.normal_matrix(lp.A, d * d) @ v
+    absA = abs(lp.A)
+    bound = absA @ (d * d * (absA.T @ np.abs(v)))
+    assert np.all(np.abs(q - ref) <= 64 * EPS * (m + np.sqrt(n)) * bound)
+    # the sketch acts row by row (B = A D W), so sampled rows of B are checked against the
+    # oracle's sketch of the same rows of A
+    B = P.ipm_sketch(ctx, M, dev(d), 0, 5, 40000, 2)
+    rows = np.sort(rng.choice(m, size=200, replace=False))
+    Bs = host(B[torch.from_numpy(rows).to("cuda:0")])
+    del B
+    Bref = osk.sketch_ADW(lp.A[rows], d, 40000, 2, 0, 5)
+    assert np.max(np.abs(Bs - Bref)) <= 1e-12 * np.max(np.abs(Bref))
+
+
+def test_config4s_full_size_solves(ctx, lp4s):
+    lp = lp4s
+    prob64 = P.Problem(_smat(lp.A, "f64"), dev(lp.b), dev(lp.c))
+    prob16 = P.Problem(_smat(lp.A, "bf16"), dev(lp.b), dev(lp.c))
+    plain = P.solve(ctx, prob64, P.Params(w=40000, s=2, seed=0))
+    print(f"\nplain {plain.iterations} iterations", flush=True)
+    mixed = P.solve(ctx, prob16, P.Params(w=40000, s=2, seed=0, precision=P.IPM_MIXED))
+    print(f"mixed {mixed.iterations} iterations", flush=True)
+    assert plain.converged and mixed.converged
+    op, om = _check(lp, plain), _check(lp, mixed)
+    lo, hi = float(lp.b @ lp.y0), float(lp.c @ lp.x0)
+    for obj in (op, om):
+        assert lo - 1e-8 * abs(lo) <= obj <= hi + 1e-8 * abs(hi)
+    assert abs(op - om) <= 1e-8 * (1 + abs(op))
