@@ -322,8 +322,11 @@ int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const
 #define IPM_KERNEL_RESID64 4   /* the mixed form's FP64-accumulated residual pass          */
 #define IPM_KERNEL_COUNT   5
 
-/* Enable (1) or disable (0) per-kernel timing with HIP events recorded around every launch of
- * the kernels above on the context's stream; enabling resets the totals. */
+/* Per-kernel timing with HIP events recorded at the start and end of launches of the kernels
+ * above on the context's stream: on = 0 disables it; on = N >= 1 times every N-th launch of each
+ * kernel (1: every launch; recording events costs a few microseconds of queue time per timed
+ * launch, so a period of 8 or more keeps the measured run close to an untimed one). Enabling
+ * resets the totals. Errors: IPM_ERR_ARG if on < 0. */
 int ipm_ctx_set_timing(ipm_ctx* ctx, int32_t on);
 /* Total milliseconds and number of launches of `kernel` since timing was enabled.
  * Synchronizes. */

@@ -93,8 +93,10 @@ class Context:
             raise IpmError(rc, msg.decode() if msg else "")
         return rc
 
-    def set_timing(self, on: bool):
-        self.check(self.lib.ipm_ctx_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, on):
+        """False/0: off; True/1: time every launch of the measured kernels; N: every N-th."""
+        period = int(on) if not isinstance(on, bool) else (1 if on else 0)
+        self.check(self.lib.ipm_ctx_set_timing(self.h, period))
 
     def kernel_time(self, kernel: int):
         ms = ctypes.c_double()

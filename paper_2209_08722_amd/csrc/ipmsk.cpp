@@ -41,6 +41,8 @@ struct ipm_ctx {
     size_t ws_bytes[W_COUNT] = {};
     void* pinned = nullptr;   // host staging for scalar readbacks
     bool timing = false;
+    int timing_period = 1;                      // time every timing_period-th launch per kernel
+    int64_t timing_seq[IPM_KERNEL_COUNT] = {};  // launches seen per kernel since timing was set
     std::vector<TimedPair> pending[IPM_KERNEL_COUNT];
     double total_ms[IPM_KERNEL_COUNT] = {};
     int64_t launches[IPM_KERNEL_COUNT] = {};
@@ -125,7 +127,7 @@ struct Timer {
     int tag;
     hipEvent_t a = nullptr, b = nullptr;
     Timer(ipm_ctx* c, int k, int t = -1) : ctx(c), kernel(k), tag(t) {
-        if (ctx->timing) {
+        if (ctx->timing && ctx->timing_seq[k]++ % ctx->timing_period == 0) {
             a = pool_event(ctx);
             b = pool_event(ctx);
             if (a && b) g_launch_timing = LaunchTiming{a, b};
@@ -503,10 +505,12 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     if (warm) CHK(warm_combination(ctx, A, d2, p, cand, ncand, cfg.acc64, dy_out, b.q, nullptr));
     HIPCHK(launch_pcg_init1(b, warm, st));
     HIPCHK(launch_pcg_init2(b, warm, dy_out, st));
-    int* hi = reinterpret_cast<int*>(ctx->pinned);
+    double* hd = reinterpret_cast<double*>(ctx->pinned);
     int j = 0;
     // first batch: the previous solve's iteration count (CG counts change slowly between IPM
-    // iterations); later batches are short so that few no-op launches follow the stop
+    // iterations); later batches are short so that few no-op launches follow the stop. Every
+    // batch ends with the finish kernel (it only reads the CG state), so the batch whose
+    // readback shows the stop already carries the result: one synchronization per batch.
     int batch = *cfg.last_iters > 4 ? *cfg.last_iters : 4;
     const int* done = ci + PI_DONE;
     for (;;) {
@@ -515,15 +519,12 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
             HIPCHK(launch_pcg_gemv1(b, j, st));
             HIPCHK(launch_pcg_gemv2(b, j, st));
         }
-        HIPCHK(hipMemcpyAsync(hi, ci, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(launch_pcg_finish(b, dy_out, info, st));
+        HIPCHK(hipMemcpyAsync(hd, info, sizeof(double) * 6, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (hi[PI_DONE] || j >= cfg.maxit) break;
+        if (hd[5] != 0.0 || j >= cfg.maxit) break;
         batch = 4;
     }
-    HIPCHK(launch_pcg_finish(b, dy_out, info, st));
-    double* hd = reinterpret_cast<double*>(ctx->pinned);
-    HIPCHK(hipMemcpyAsync(hd, info, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
     out->iters = (int)hd[0];
     out->status = (int)hd[1];
     out->warm_used = (int)hd[2];
@@ -746,6 +747,7 @@ const char* ipm_last_error(const ipm_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 int ipm_ctx_set_timing(ipm_ctx* ctx, int32_t on) {
     if (!ctx) return IPM_ERR_ARG;
+    if (on < 0) return fail(ctx, IPM_ERR_ARG, "timing period must be >= 0");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
     for (int k = 0; k < IPM_KERNEL_COUNT; ++k) {
         resolve_timing(ctx, k, INT_MAX);
@@ -753,6 +755,8 @@ int ipm_ctx_set_timing(ipm_ctx* ctx, int32_t on) {
         ctx->launches[k] = 0;
     }
     ctx->timing = on != 0;
+    ctx->timing_period = on > 0 ? on : 1;
+    for (int k = 0; k < IPM_KERNEL_COUNT; ++k) ctx->timing_seq[k] = 0;
     return IPM_OK;
 }
 
@@ -1021,11 +1025,10 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
     HIPCHK(launch_roots(n, state->x, state->s, dx, ds, prm->gamma, scal, partmin, st));
     HIPCHK(launch_alpha(n, partmin, Gn, prm->gamma, prm->theta, prm->min_step, scal, st));
     HIPCHK(launch_update(n, m, state->x, state->y, state->s, dx, dyv, ds, scal, st));
-    HIPCHK(launch_dot(m, dyv, dyv, sq + 2, st));
+    HIPCHK(launch_dot(m, dyv, dyv, scal + SC_DY2, st));
     HIPCHK(hipMemcpyAsync(hs, scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hs + SC_COUNT, sq + 2, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    info->dy_norm = std::sqrt(hs[SC_COUNT]);
+    info->dy_norm = std::sqrt(hs[SC_DY2]);
     info->alpha_max = hs[SC_AMAX];
     info->alpha = hs[SC_ABAR];
     info->vnorm = std::sqrt(hs[SC_V2]);

@@ -9,7 +9,7 @@ namespace ipmsk {
 enum Scalar {
     SC_XS = 0, SC_CTX, SC_C2, SC_MU, SC_SMU, SC_BTY, SC_B2, SC_RP2, SC_RD2,
     SC_GAP, SC_RELGAP, SC_RPREL, SC_RDREL, SC_OBJ, SC_RNORM, SC_MU0, SC_R0NORM,
-    SC_A1, SC_A2, SC_V2, SC_AMAX, SC_ABAR, SC_STALL, SC_ROOT, SC_COUNT = 32
+    SC_A1, SC_A2, SC_V2, SC_AMAX, SC_ABAR, SC_STALL, SC_ROOT, SC_DY2, SC_COUNT = 32
 };
 
 // Post-processing of the row reduction of strip-pass partials.

@@ -277,6 +277,7 @@ __global__ __launch_bounds__(GNT) void k_pcg_finish(PcgBufs b, double* __restric
         info[2] = (double)b.ci[PI_WARM];
         info[3] = rs > 0.0 ? b.cd[PD_HIST + it] / sqrt(rs) : 0.0;
         info[4] = rs;
+        info[5] = (double)b.ci[PI_DONE];
     }
 }
 
