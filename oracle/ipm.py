@@ -24,6 +24,11 @@ TEST INFRASTRUCTURE (oracle). Plain FP64 NumPy/SciPy, written from the paper:
   N(gamma) = {x_i s_i >= (1-gamma) mu, ||r|| / ||r0|| <= mu / mu0} (Section 5),
   with a backoff theta when it is below 1; alpha_bar minimises mu(alpha) on
   [0, alpha_max]. Update (Algorithm 3, step 8).
+* Feasible variant (Params.feasible; Algorithm 2, Section 4) from a strictly
+  feasible point: p = A x - sigma mu A S^{-1} 1 (eqn. pdef), ds = -A^T dy
+  (eq. dels), the same dx with v (eq. delxhat), and the neighbourhood
+  N(gamma) = {x_i s_i >= (1-gamma) mu} without a residual term (eq. neigh);
+  alpha_bar minimises (x + alpha dx)^T (s + alpha ds) on [0, alpha_max].
 
 Where the paper is silent the following readings apply (both the oracle and
 the GPU library implement them): gamma = 0.9, sigma = 0.5, theta = 0.9999;
@@ -72,6 +77,7 @@ class Params:
     min_step: float = 1e-14
     max_redraws: int = 3
     max_shifts: int = 3
+    feasible: bool = False      # Algorithm 2 instead of Algorithm 3
 
 
 @dataclass
@@ -113,6 +119,13 @@ def initial_state(A: np.ndarray, b: np.ndarray, c: np.ndarray) -> State:
     return st
 
 
+def feasible_state(A, x0: np.ndarray, y0: np.ndarray, s0: np.ndarray) -> State:
+    """A strictly feasible start (x0, y0, s0) for Algorithm 2; mu0 taken there, no residual
+    reference (the feasible neighbourhood has no residual term)."""
+    n = A.shape[1]
+    return State(x0.copy(), y0.copy(), s0.copy(), 0, float(x0 @ s0 / n), 0.0)
+
+
 def normal_matrix(A, d2) -> np.ndarray:
     """M = A diag(d2) A^T as a dense m x m array (A dense or scipy sparse)."""
     if sp.issparse(A):
@@ -128,6 +141,11 @@ def residuals(A, b, c, x, y, s):
 def rhs_p(A, b, x, s, rd, sigma, mu):
     """p = b - A (sigma mu / s + d^2 r_d), the infeasible right-hand side of Section 5."""
     return b - A @ (sigma * mu / s + (x / s) * rd)
+
+
+def rhs_p_feasible(A, x, s, sigma, mu):
+    """p = -sigma mu A S^{-1} 1 + A x, the feasible right-hand side (Section 4, eqn. pdef)."""
+    return A @ x - sigma * mu * (A @ (1.0 / s))
 
 
 def rhs_p_paper_form(A, b, x, s, rd, sigma, mu):
@@ -358,7 +376,8 @@ def shifted_cholesky(Q: np.ndarray, max_shifts: int):
 
 def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
          keep: bool = False) -> tuple:
-    """One iteration of Algorithm 3 from state ``st``; returns (new_state, StepInfo).
+    """One iteration of Algorithm 3 (Algorithm 2 when prm.feasible) from state ``st``; returns
+    (new_state, StepInfo).
 
     mode "exact": A D^2 A^T dy = p solved by Cholesky, v = 0 (IPM with a direct
     solver). mode "sketch": Algorithm 1 with the hash sketch of oracle.sketch and
@@ -377,7 +396,7 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
         info.status = CONVERGED
         return st, info
     d2 = x / s
-    p = rhs_p(A, b, x, s, rd, prm.sigma, mu)
+    p = rhs_p_feasible(A, x, s, prm.sigma, mu) if prm.feasible else rhs_p(A, b, x, s, rd, prm.sigma, mu)
 
     def matvec(v):
         return A @ (d2 * (A.T @ v))
@@ -425,10 +444,11 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
             v = np.sqrt(x * s) * (W @ u)
         if keep:
             info.extra.update(B=B, Q=Q, L=L, pcg=res)
-    ds = -rd - A.T @ dy
+    ds = -(A.T @ dy) if prm.feasible else -rd - A.T @ dy
     dx = -x + prm.sigma * mu / s - d2 * ds - v / s
     rnorm = float(np.sqrt(rp @ rp + rd @ rd))
-    amax, abar, aux = step_lengths(x, s, dx, ds, prm.gamma, prm.theta, st.mu0, st.r0norm, rnorm)
+    r0ref = 0.0 if prm.feasible else st.r0norm     # no residual term in the feasible N(gamma)
+    amax, abar, aux = step_lengths(x, s, dx, ds, prm.gamma, prm.theta, st.mu0, r0ref, rnorm)
     info.alpha_max, info.alpha = amax, abar
     info.vnorm = float(np.linalg.norm(v))
     if keep:
@@ -452,7 +472,8 @@ class SolveResult:
 
 def solve(A, b, c, prm: Params, mode: str = "sketch", st: Optional[State] = None,
           callback=None) -> SolveResult:
-    """Run Algorithm 3 from x = s = 1, y = 0 until the stop test holds or maxit_ipm."""
+    """Run Algorithm 3 from x = s = 1, y = 0 (or Algorithm 2 from ``st``, which must then be
+    strictly feasible, when prm.feasible) until the stop test holds or maxit_ipm."""
     st = initial_state(A, b, c) if st is None else st
     infos = []
     for _ in range(prm.maxit_ipm + 1):
