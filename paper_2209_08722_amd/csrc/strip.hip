@@ -30,6 +30,33 @@ constexpr int kRrNt = 512;   // re-read form: threads per block
 constexpr int kRrCh = 4;     // re-read form: rows per thread per chunk
 
 // Sum of the per-block partials part[acc][row][block] and the RowPost step: one wave per row.
+// R 16-byte words of one column segment, rows g + RG k (k < R), rows >= m read as zero. seg is
+// the segment's address in row g and seg0 its address in row 0. A segment inside A (left >=
+// VEC elements) is read without branches: rows past the end read row 0 and are masked, so all
+// R loads are in flight together (per-row branches made the compiler wait for each load before
+// the next). A segment crossing the end of the row (last strip only) is read element by element.
+template <typename T, int R, bool STREAM>
+__device__ __forceinline__ void load_segment(const T* seg, const T* seg0, int64_t rowstride, int g, int RG, int m,
+                                             int64_t left, uint4* av) {
+    constexpr int VEC = Elem<T>::VEC;
+    if (left >= VEC) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const bool ok = g + RG * k < m;
+            const T* p = ok ? seg + (int64_t)k * rowstride : seg0;
+            const uint4 w = STREAM ? raw16_stream(p) : Elem<T>::raw16(p);
+            const uint32_t msk = ok ? 0xffffffffu : 0u;
+            av[k] = make_uint4(w.x & msk, w.y & msk, w.z & msk, w.w & msk);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const bool ok = g + RG * k < m && left > 0;
+            av[k] = ok ? raw_partial<T>(seg + (int64_t)k * rowstride, (int)left) : make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+}
+
 constexpr int RNT = 256;
 __global__ __launch_bounds__(RNT) void k_rowsum(StripCall a, int G, int nacc, int ncr) {
     if (a.done != nullptr && *a.done) return;
@@ -55,7 +82,7 @@ __global__ __launch_bounds__(RNT) void k_rowsum(StripCall a, int G, int nacc, in
                 case POST_RESID: {
                     const double rp = t0 - a.b[i];
                     a.out0[i] = rp;
-                    a.out1[i] = a.b[i] - t1;
+                    a.out1[i] = a.feasible ? t0 - t1 : a.b[i] - t1;   // p (eqn. pdef when feasible)
                     contrib = rp * rp;
                     break;
                 }
@@ -128,14 +155,8 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) pfv[e] = Op::PF ? Op::pre(a, j0 + e, j0 + e < a.n) : 0.0;
         uint4 av[RPT];
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const int i = g + RG * k;
-            const T* ptr = A + (int64_t)strip * SW + (int64_t)(RG * k) * a.ld + lane_off;
-            if (i < m && left >= VEC) av[k] = raw16_stream(ptr);
-            else if (i < m && left > 0) av[k] = raw_partial<T>(ptr, (int)left);
-            else av[k] = make_uint4(0u, 0u, 0u, 0u);
-        }
+        load_segment<T, RPT, true>(A + (int64_t)strip * SW + lane_off, A + (int64_t)strip * SW + c * VEC,
+                                   (int64_t)RG * a.ld, g, RG, m, left, av);
         // column dots over this thread's rows
         ACC pd[VEC];
 #pragma unroll
@@ -274,14 +295,9 @@ __global__ __launch_bounds__(NT) void k_strip_rr(StripCall a, int nstrips, int K
         for (int e = 0; e < VEC; ++e) pd[e] = (ACC)0;
         for (int k0 = 0; k0 < K; k0 += CH) {
             uint4 av[CH];
-#pragma unroll
-            for (int kk = 0; kk < CH; ++kk) {
-                const int i = g + RG * (k0 + kk);
-                const T* ptr = A + (int64_t)strip * SW + (int64_t)(RG * (k0 + kk)) * a.ld + lane_off;
-                if (i < m && left >= VEC) av[kk] = Elem<T>::raw16(ptr);
-                else if (i < m && left > 0) av[kk] = raw_partial<T>(ptr, (int)left);
-                else av[kk] = make_uint4(0u, 0u, 0u, 0u);
-            }
+            load_segment<T, CH, false>(A + (int64_t)strip * SW + (int64_t)(RG * k0) * a.ld + lane_off,
+                                       A + (int64_t)strip * SW + c * VEC, (int64_t)RG * a.ld, g + RG * k0, RG, m,
+                                       left, av);
 #pragma unroll
             for (int kk = 0; kk < CH; ++kk) {
                 const ACC vv = vs[g + RG * (k0 + kk)];
@@ -316,14 +332,9 @@ __global__ __launch_bounds__(NT) void k_strip_rr(StripCall a, int nstrips, int K
         }
         for (int k0 = 0; k0 < K; k0 += CH) {
             uint4 av[CH];
-#pragma unroll
-            for (int kk = 0; kk < CH; ++kk) {
-                const int i = g + RG * (k0 + kk);
-                const T* ptr = A + (int64_t)strip * SW + (int64_t)(RG * (k0 + kk)) * a.ld + lane_off;
-                if (i < m && left >= VEC) av[kk] = Elem<T>::raw16(ptr);
-                else if (i < m && left > 0) av[kk] = raw_partial<T>(ptr, (int)left);
-                else av[kk] = make_uint4(0u, 0u, 0u, 0u);
-            }
+            load_segment<T, CH, false>(A + (int64_t)strip * SW + (int64_t)(RG * k0) * a.ld + lane_off,
+                                       A + (int64_t)strip * SW + c * VEC, (int64_t)RG * a.ld, g + RG * k0, RG, m,
+                                       left, av);
 #pragma unroll
             for (int kk = 0; kk < CH; ++kk)
 #pragma unroll
