@@ -96,14 +96,16 @@ def cpu_baseline(lp, budget_s: float):
                       f"(dense Cholesky of A D^2 A^T) FP64 IPM, {el:.1f} s wall"}
 
 
-def timed_solve(P, ctx, prob, prm, net=None, timing=False):
-    """One full solve from x = s = 1, y = 0, wall-clocked between device synchronizations."""
+def timed_solve(P, ctx, prob, prm, net=None, timing=False, start=None):
+    """One full solve from x = s = 1, y = 0 (or from ``start()``, a fresh State), wall-clocked
+    between device synchronizations."""
     import torch
+    st = start() if start is not None else None
     torch.cuda.synchronize()
     if timing:
         ctx.set_timing(True)
     t0 = time.perf_counter()
-    res = P.solve(ctx, prob, prm, net=net)
+    res = P.solve(ctx, prob, prm, net=net, st=st)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     kt = {}
@@ -124,6 +126,29 @@ def timed_solve(P, ctx, prob, prm, net=None, timing=False):
         "final_relgap": last["relgap"], "final_rp_rel": last["rp_rel"], "final_rd_rel": last["rd_rel"],
         "objective": last["obj"], "kernels": kt,
     }
+
+
+def algorithm2_comparison(P, ctx, lp, prob, w, s):
+    """The feasible IPM (Algorithm 2) from the generator's strictly feasible pair against the
+    infeasible IPM (Algorithm 3) from x = s = 1, y = 0 on the same LP: one warm-up solve each,
+    then one timed solve each."""
+    import torch
+    from dataclasses import replace
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    n = lp.A.shape[1]
+
+    def witness():
+        return P.State(dev(lp.x0), dev(lp.y0), dev(lp.s0), 0, float(lp.x0 @ lp.s0) / n, 0.0)
+
+    base = P.Params(w=w, s=s, seed=0)
+    out = {}
+    for name, prm, start in (("algorithm3_infeasible", base, None),
+                             ("algorithm2_feasible", replace(base, feasible=1), witness)):
+        timed_solve(P, ctx, prob, prm, start=start)
+        out[name] = timed_solve(P, ctx, prob, prm, start=start)
+        out[name].pop("kernels", None)
+        log(f"  {name}: {out[name]['iterations']} iterations, {out[name]['iter_per_s']:.1f} it/s")
+    return out
 
 
 def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
@@ -346,6 +371,8 @@ def main() -> int:
         "gram_tflops": gr_tf,
         "gram_mfma_frac": (gr_tf / FP64_MFMA_PEAK_TFLOPS) if gr_tf else None,
     }
+    log("feasible (Algorithm 2) vs infeasible (Algorithm 3) IPM")
+    out["algorithms"] = algorithm2_comparison(P, ctx, lp, prob, w, s)
     if args.forms != "none":
         out["forms"] = forms_comparison(P, ctx, args.forms, args.train_seeds, args.epochs)
     if not args.no_cpu_baseline:

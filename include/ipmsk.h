@@ -141,12 +141,19 @@ typedef struct {
     int32_t max_shifts;  /* when Q = B B^T fails to factor: retries with Q + delta_j I,
                             delta_j = 2^-53 trace(Q) 100^j, j < max_shifts, before the next
                             draw of W (the FP64 Gram squares the condition of B)              */
+    int32_t feasible;    /* 0: Algorithm 3 (infeasible IPM). 1: Algorithm 2 (feasible IPM,
+                            Section 4), for a strictly feasible (x, y, s): p = A x -
+                            sigma mu A S^-1 1 (eqn. pdef), ds = -A^T dy (eq. dels), dx as in
+                            eq. delxhat, and N(gamma) without its residual term (eq. neigh).
+                            The residuals are still measured for the stop test.            */
+    int32_t solver;      /* IPM_SOLVER_CG (the only value accepted)                         */
     uint64_t seed;       /* sketch seed                                                     */
 } ipm_params;
 
 #define IPM_PLAIN 0
 #define IPM_MIXED 1
 #define IPM_MIXED_F32ACC 2
+#define IPM_SOLVER_CG      0   /* preconditioned conjugate gradients (Algorithm 1, step 3)   */
 #define IPM_WARM_NONE 0
 #define IPM_WARM_PREV 1
 #define IPM_WARM_GIVEN 2

@@ -234,12 +234,14 @@ class Params:
     inner_tol: float = 1e-4
     max_refine: int = 12
     max_shifts: int = 3
+    feasible: int = 0              # 1: Algorithm 2 from a strictly feasible state
+    solver: int = 0                # IPM_SOLVER_CG
 
     def c(self) -> IpmParams:
         return IpmParams(self.sigma, self.gamma, self.theta, self.tol_pcg, self.gap_tol, self.min_step,
                          self.stag_ratio, self.w, self.s, self.maxit_pcg, self.stag_window, self.max_redraws,
                          self.vcorr, self.precision, self.warm_start, self.inner_tol, self.max_refine,
-                         self.max_shifts, self.seed & ((1 << 64) - 1))
+                         self.max_shifts, self.feasible, self.solver, self.seed & ((1 << 64) - 1))
 
 
 def ipm_normal_matvec(ctx: Context, A: Matrix, d2, v):

@@ -231,12 +231,13 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // (entry c is l_cc) and updates the row with uniform-address (broadcast) reads of that column; for
 // j > t the update only touches the unused upper part. Wave 1, lane t, keeps column t of the
 // inverse and does step c of the column-oriented forward substitution L x = e_t with the same
-// published column (x_c = y_c / l_cc, then y_i -= l_ic x_c for i > c), storing X's row c
+// published column and 1/l_cc (x_c = y_c / l_cc, then y_i -= l_ic x_c for i > c), storing X's row c
 // (coalesced). L goes back through LDS for a coalesced write. A pivot that is not positive is
 // recorded in *status (smallest index wins) and replaced by 1 so the remaining work stays finite.
 __global__ __launch_bounds__(128) void k_potrf_diag(double* __restrict__ Lw, int64_t ld, int k0, int kb,
                                                     double* __restrict__ X, int64_t ldx, int* __restrict__ status) {
     __shared__ double col[2][64];
+    __shared__ double rinv[64];          // 1 / l_cc
     __shared__ double Ls[64][65];
     const int lane = threadIdx.x & 63;
     const bool fac = threadIdx.x < 64;   // wave 0 factors, wave 1 inverts
@@ -261,9 +262,13 @@ __global__ __launch_bounds__(128) void k_potrf_diag(double* __restrict__ Lw, int
                 bad = min(bad, k0 + c);
                 piv = 1.0;
             }
-            const double lcc = sqrt(piv);
-            z[c] = (lane == c) ? lcc : z[c] * (1.0 / lcc);
+            // 1/sqrt and sqrt from one reciprocal square root (shorter dependency chain than a
+            // square root followed by a division; the factor only has to be accurate to rounding)
+            const double inv = rsqrt(piv);
+            const double lcc = piv * inv;
+            z[c] = (lane == c) ? lcc : z[c] * inv;
             cc[lane] = z[c];
+            if (lane == 0) rinv[c] = inv;
             Ls[lane][c] = z[c];            // L[lane][c], final
         }
         __syncthreads();
@@ -272,7 +277,7 @@ __global__ __launch_bounds__(128) void k_potrf_diag(double* __restrict__ Lw, int
 #pragma unroll
             for (int j = c + 1; j < 64; ++j) z[j] = fma(-ltc, cc[j], z[j]);
         } else {
-            z[c] = z[c] / cc[c];           // X[c][lane], final
+            z[c] = z[c] * rinv[c];         // X[c][lane], final
             if (xw && c < kb) xcol[(int64_t)c * ldx] = z[c];
             const double xc = z[c];
 #pragma unroll

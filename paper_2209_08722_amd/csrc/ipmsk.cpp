@@ -651,6 +651,8 @@ int check_solver_params(ipm_ctx* ctx, const ipm_params* p) {
     if (!(p->inner_tol > 0 && p->inner_tol < 1)) return fail(ctx, IPM_ERR_ARG, "inner_tol must be in (0, 1)");
     if (p->max_refine < 1 || p->max_refine > 1000) return fail(ctx, IPM_ERR_ARG, "max_refine out of range");
     if (p->max_shifts < 0 || p->max_shifts > 8) return fail(ctx, IPM_ERR_ARG, "max_shifts out of range");
+    if (p->feasible != 0 && p->feasible != 1) return fail(ctx, IPM_ERR_ARG, "feasible must be 0 or 1");
+    if (p->solver != IPM_SOLVER_CG) return fail(ctx, IPM_ERR_ARG, "unknown solver %d", p->solver);
     return IPM_OK;
 }
 
@@ -901,11 +903,12 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         c.out0 = rp;
         c.out1 = p;
         c.outsc = sq;
+        c.feasible = prm->feasible;
         CHK(run_pass(ctx, A, c, -1, -1));
     }
     const int set_ref = state->r0norm < 0.0 ? 1 : 0;
     HIPCHK(launch_metrics(n, m, ctx->ws[W_GPART] ? reinterpret_cast<double*>(ctx->ws[W_GPART]) : nullptr,
-                          rowsum_blocks(m), sq + 1, set_ref, state->mu0, state->r0norm, scal, st));
+                          rowsum_blocks(m), sq + 1, set_ref, state->mu0, state->r0norm, prm->feasible, scal, st));
     double* hs = reinterpret_cast<double*>(ctx->pinned);
     HIPCHK(hipMemcpyAsync(hs, scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1009,6 +1012,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         c.post = POST_RHAT;
         c.pvec = p;
         c.out0 = rhat;
+        c.feasible = prm->feasible;
         CHK(run_pass(ctx, A, c, -1, -1));
     }
     double* u = nullptr;

@@ -66,6 +66,7 @@ struct StripCall {
     const int64_t* col_ptr;  // n + 1
     const int32_t* row_idx;  // nnz
     double* coefs;           // [nacc][n] column coefficients between the two sparse passes
+    int feasible;            // resid / dir passes of Algorithm 2: r_d taken as 0, p = A x - A sigma mu / s
 };
 
 StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind);
@@ -165,7 +166,7 @@ hipError_t launch_stats(int64_t n, const double* x, const double* s, const doubl
 hipError_t launch_fin_stats(int64_t n, int m, const double* part3, int G, const double* b, const double* y,
                             double sigma, double* scal, hipStream_t st);
 hipError_t launch_metrics(int64_t n, int m, const double* rp2part, int Grp, const double* rd2, int set_ref,
-                          double mu0_in, double r0_in, double* scal, hipStream_t st);
+                          double mu0_in, double r0_in, int feasible, double* scal, hipStream_t st);
 hipError_t launch_fin_dx(const double* part3, int G, double* scal, hipStream_t st);
 hipError_t launch_roots(int64_t n, const double* x, const double* s, const double* dx, const double* ds,
                         double gamma, const double* scal, double* partmin, hipStream_t st);

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(RNT_S) void k_csr_rows(StripCall a, int nacc, int n
                 case POST_RESID: {
                     const double rp = t0 - a.b[i];
                     a.out0[i] = rp;
-                    a.out1[i] = a.b[i] - t1;
+                    a.out1[i] = a.feasible ? t0 - t1 : a.b[i] - t1;   // p (eqn. pdef when feasible)
                     contrib = rp * rp;
                     break;
                 }

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(PNT) void k_fin_stats(int64_t n, int m, const doubl
 // Stop-test quantities at the current point; on the first call (set_ref) also mu0 and ||r0||.
 __global__ __launch_bounds__(PNT) void k_metrics(int64_t n, int m, const double* __restrict__ rp2part, int Grp,
                                                  const double* __restrict__ rd2p, int set_ref, double mu0_in,
-                                                 double r0_in, double* __restrict__ scal) {
+                                                 double r0_in, int feasible, double* __restrict__ scal) {
     __shared__ double sh[4];
     const double rp2 = sum_partials(rp2part, Grp, 1, sh);
     const double rd2 = *rd2p;
@@ -74,7 +74,8 @@ __global__ __launch_bounds__(PNT) void k_metrics(int64_t n, int m, const double*
         const double rn = sqrt(rp2 + rd2);
         scal[SC_RNORM] = rn;
         scal[SC_MU0] = set_ref ? scal[SC_MU] : mu0_in;
-        scal[SC_R0NORM] = set_ref ? rn : r0_in;
+        // the feasible N(gamma) has no residual term: a zero reference switches it off
+        scal[SC_R0NORM] = feasible ? 0.0 : (set_ref ? rn : r0_in);
     }
 }
 
@@ -218,8 +219,9 @@ hipError_t launch_fin_stats(int64_t n, int m, const double* part3, int G, const 
 }
 
 hipError_t launch_metrics(int64_t n, int m, const double* rp2part, int Grp, const double* rd2, int set_ref,
-                          double mu0_in, double r0_in, double* scal, hipStream_t st) {
-    hipLaunchKernelGGL(k_metrics, dim3(1), dim3(PNT), 0, st, n, m, rp2part, Grp, rd2, set_ref, mu0_in, r0_in, scal);
+                          double mu0_in, double r0_in, int feasible, double* scal, hipStream_t st) {
+    hipLaunchKernelGGL(k_metrics, dim3(1), dim3(PNT), 0, st, n, m, rp2part, Grp, rd2, set_ref, mu0_in, r0_in,
+                       feasible, scal);
     return hipGetLastError();
 }
 

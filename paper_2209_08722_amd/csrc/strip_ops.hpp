@@ -5,6 +5,7 @@
 //   OpResid:  r_d = t + s_j - c_j (stored, sum of squares kept); coefs x_j and
 //             sigma mu / s_j + d2_j r_d                         (residual pass, Sec. 5)
 //   OpDir:    ds_j = -r_d,j - t (stored); coef = d2_j t          (direction pass, eq. ipm_inf)
+// For Algorithm 2 (a.feasible) r_d is taken as 0 in the coefficient and in ds (eqns. pdef, dels).
 #pragma once
 
 #include "kernels.hpp"
@@ -38,7 +39,7 @@ struct OpResid {
         const double rdj = (double)dot + sj - a.c[j];
         if (writer) { a.rd_out[j] = rdj; cr[0] += rdj * rdj; }
         coef[0] = (ACC)a.x[j];
-        coef[1] = (ACC)(st.smu / sj + a.d2[j] * rdj);
+        coef[1] = (ACC)(a.feasible ? st.smu / sj : st.smu / sj + a.d2[j] * rdj);
     }
 };
 
@@ -53,7 +54,7 @@ struct OpDir {
                                   ACC* coef, double*, double) {
         if (!valid) { coef[0] = (ACC)0; return; }
         const double t = (double)dot;
-        if (writer) a.ds_out[j] = -a.rd[j] - t;
+        if (writer) a.ds_out[j] = a.feasible ? -t : -a.rd[j] - t;
         coef[0] = (ACC)(a.d2[j] * t);
     }
 };

@@ -59,7 +59,8 @@ class IpmParams(ctypes.Structure):
                 ("gap_tol", c_double), ("min_step", c_double), ("stag_ratio", c_double),
                 ("w", c_int32), ("s", c_int32), ("maxit_pcg", c_int32), ("stag_window", c_int32),
                 ("max_redraws", c_int32), ("vcorr", c_int32), ("precision", c_int32), ("warm_start", c_int32),
-                ("inner_tol", c_double), ("max_refine", c_int32), ("max_shifts", c_int32), ("seed", c_uint64)]
+                ("inner_tol", c_double), ("max_refine", c_int32), ("max_shifts", c_int32), ("feasible", c_int32),
+                ("solver", c_int32), ("seed", c_uint64)]
 
 
 class IpmPcgInfo(ctypes.Structure):
