@@ -121,6 +121,7 @@ def timed_solve(P, ctx, prob, prm, net=None, timing=False, start=None):
         "converged": bool(res.converged), "iterations": res.iterations, "seconds": el,
         "iter_per_s": res.iterations / el if el > 0 else None,
         "cg_iterations": int(sum(i["pcg_iters"] for i in steps)),
+        "max_cg_iterations": int(max([i["pcg_iters"] for i in steps] or [0])),
         "refine_rounds": int(sum(i["refine_rounds"] for i in steps)),
         "warm_kept": int(sum(i["warm_used"] for i in steps)),
         "final_relgap": last["relgap"], "final_rp_rel": last["rp_rel"], "final_rd_rel": last["rd_rel"],
@@ -148,6 +149,28 @@ def algorithm2_comparison(P, ctx, lp, prob, w, s):
         out[name] = timed_solve(P, ctx, prob, prm, start=start)
         out[name].pop("kernels", None)
         log(f"  {name}: {out[name]['iterations']} iterations, {out[name]['iter_per_s']:.1f} it/s")
+    return out
+
+
+def vcorr_ablation(P, ctx):
+    """The paper's no-correction comparison (Section 7): the IPM with and without the
+    perturbation v on l1-SVM LPs of the experiments' four shapes and sketch widths (Table 1),
+    synthetic data; outer iterations, largest and total inner (CG) iterations, time."""
+    import lpgen
+    out = {}
+    for name, sh in lpgen.SVM_SHAPES.items():
+        lp = lpgen.svm_lp(sh["m"], sh["N"], seed=0)
+        prob = P.Problem.from_lp(lp)
+        rec = {"lp_shape": list(lp.A.shape), "w": sh["w"]}
+        for tag, v in (("with_v", 1), ("without_v", 0)):
+            prm = P.Params(w=sh["w"], s=2, seed=0, vcorr=v)
+            timed_solve(P, ctx, prob, prm)
+            r = timed_solve(P, ctx, prob, prm)
+            rec[tag] = {k: r[k] for k in ("converged", "iterations", "max_cg_iterations", "cg_iterations",
+                                          "seconds", "objective", "final_relgap")}
+        log(f"  {name} {lp.A.shape}: outer {rec['with_v']['iterations']} / {rec['without_v']['iterations']}, "
+            f"inner sum {rec['with_v']['cg_iterations']} / {rec['without_v']['cg_iterations']} (with / without v)")
+        out[name] = rec
     return out
 
 
@@ -373,6 +396,8 @@ def main() -> int:
     }
     log("feasible (Algorithm 2) vs infeasible (Algorithm 3) IPM")
     out["algorithms"] = algorithm2_comparison(P, ctx, lp, prob, w, s)
+    log("v-correction ablation on l1-SVM LPs")
+    out["v_correction_ablation"] = vcorr_ablation(P, ctx)
     if args.forms != "none":
         out["forms"] = forms_comparison(P, ctx, args.forms, args.train_seeds, args.epochs)
     if not args.no_cpu_baseline:

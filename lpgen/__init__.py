@@ -27,8 +27,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["LP", "dense_lp", "sparse_lp", "tiny_lp", "config", "bf16_round", "f32_round",
-           "CONFIGS", "mlp_init"]
+__all__ = ["LP", "dense_lp", "sparse_lp", "svm_lp", "tiny_lp", "config", "bf16_round", "f32_round",
+           "CONFIGS", "SVM_SHAPES", "mlp_init"]
 
 
 @dataclass
@@ -118,6 +118,46 @@ def sparse_lp(m: int, n: int, density: float, seed: int = 0, storage: str = "f64
     A.sort_indices()
     b, c, x0, y0, s0 = _witness(rng, A)
     return LP(A, b, c, x0, y0, s0, storage=storage, name=name or f"sparse{m}x{n}s{seed}")
+
+
+def svm_lp(m: int, N: int, seed: int = 0, k: int = 10, density: float = 1.0, name: str = "") -> LP:
+    """l1-regularised SVM as a standard-form LP (the experiments' application, Section 7 and the
+    appendix on SVMs), on synthetic data: m training points x_i in R^N with N(0, 1) features
+    (a fraction ``density`` of them nonzero), labels y_i = sign(x_i^T beta) for a k-sparse
+    N(0, 1) beta (separable through the origin, so the LP is feasible). Variables w+, w- (N each)
+    and surplus t (m): minimise 1^T (w+ + w-) subject to y_i x_i^T (w+ - w-) - t_i = 1,
+    (w+, w-, t) >= 0, i.e. A = [Y X, -Y X, -I] (m x (2N + m)), b = 1, c = [1, 1, 0]. The bias b'
+    of the SVM is left out (its split into two free parts with zero cost would make the optimal
+    face unbounded). Draw order: beta's support, beta, features (pattern first when sparse).
+    No witness pair is drawn (x0, y0, s0 are None)."""
+    rng = np.random.default_rng(seed)
+    supp = rng.choice(N, size=min(k, N), replace=False)
+    beta = np.zeros(N)
+    beta[supp] = rng.standard_normal(supp.size)
+    if density < 1.0:
+        mask = rng.random((m, N)) < density
+        X = np.where(mask, rng.standard_normal((m, N)), 0.0)
+    else:
+        X = rng.standard_normal((m, N))
+    y = np.sign(X @ beta)
+    y[y == 0] = 1.0
+    YX = y[:, None] * X
+    A = np.hstack([YX, -YX, -np.eye(m)])
+    b = np.ones(m)
+    c = np.concatenate([np.ones(2 * N), np.zeros(m)])
+    lp = LP(A, b, c, None, None, None, storage="f64", name=name or f"svm{m}x{N}s{seed}")
+    lp.meta.update(features=X, labels=y)
+    return lp
+
+
+# The experiments' four l1-SVM shapes (m training points x N features) and sketch widths
+# (Section 7, Table 1); synthetic stand-ins for the UCI data sets named there.
+SVM_SHAPES = {
+    "arcene": dict(m=100, N=10_000, w=200),
+    "dexter": dict(m=300, N=20_000, w=500),
+    "drivface": dict(m=606, N=6400, w=1000),
+    "gene_rna": dict(m=801, N=20_531, w=2000),
+}
 
 
 def tiny_lp(m: int, n: int, seed: int) -> LP:
