@@ -271,6 +271,8 @@ def main() -> int:
     ap.add_argument("--workload", default="1", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the Algorithm 2 comparison and the v-correction ablation")
     ap.add_argument("--forms", default="3", choices=["3", "4d", "none"],
                     help="workload of the plain vs mixed+learned comparison")
     ap.add_argument("--train-seeds", type=int, default=8)
@@ -394,10 +396,11 @@ def main() -> int:
         "gram_tflops": gr_tf,
         "gram_mfma_frac": (gr_tf / FP64_MFMA_PEAK_TFLOPS) if gr_tf else None,
     }
-    log("feasible (Algorithm 2) vs infeasible (Algorithm 3) IPM")
-    out["algorithms"] = algorithm2_comparison(P, ctx, lp, prob, w, s)
-    log("v-correction ablation on l1-SVM LPs")
-    out["v_correction_ablation"] = vcorr_ablation(P, ctx)
+    if not args.no_extras:
+        log("feasible (Algorithm 2) vs infeasible (Algorithm 3) IPM")
+        out["algorithms"] = algorithm2_comparison(P, ctx, lp, prob, w, s)
+        log("v-correction ablation on l1-SVM LPs")
+        out["v_correction_ablation"] = vcorr_ablation(P, ctx)
     if args.forms != "none":
         out["forms"] = forms_comparison(P, ctx, args.forms, args.train_seeds, args.epochs)
     if not args.no_cpu_baseline:
