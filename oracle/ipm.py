@@ -14,6 +14,8 @@ TEST INFRASTRUCTURE (oracle). Plain FP64 NumPy/SciPy, written from the paper:
   norm ||Q^{-1/2} r|| equals ||L^{-1} r||, so Cholesky replaces the SVD.
   Stopping: ||L^{-1} r_j|| <= tol * ||L^{-1} p|| (eq. pdcond2 with a tolerance
   in place of the fixed iteration count t).
+* Params.sketch = 1 replaces the sparse embedding by a Gaussian W (the experiments' choice,
+  Section 7; oracle.sketch.gaussian_rows), the same W serving Q and v.
 * Perturbation v = (XS)^{1/2} W (ADW)^+ (A D^2 A^T dy - p) (Section 4,
   eq. compv) with (ADW)^+ = B^T Q^{-1} since B has full row rank (Lemma
   fullrankR). The residual is the true one, recomputed from dy.
@@ -47,7 +49,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from .sketch import sketch_ADW, sketch_matrix
+from .sketch import gaussian_apply, sketch_ADW, sketch_gaussian, sketch_matrix
 
 # status values (oracle-side names)
 OK = 0
@@ -78,6 +80,7 @@ class Params:
     max_redraws: int = 3
     max_shifts: int = 3
     feasible: bool = False      # Algorithm 2 instead of Algorithm 3
+    sketch: int = 0             # 0: sparse embedding (Section 2); 1: Gaussian W (Section 7)
 
 
 @dataclass
@@ -417,7 +420,10 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
         for attempt in range(prm.max_redraws + 1):
             w, sk = sketch_size(prm.w, prm.s, attempt)
             key = sketch_seed(prm.seed, attempt)
-            B = sketch_ADW(A, np.sqrt(d2), w, sk, key, st.k)
+            if prm.sketch == 1:
+                B = sketch_gaussian(A, np.sqrt(d2), w, key, st.k)
+            else:
+                B = sketch_ADW(A, np.sqrt(d2), w, sk, key, st.k)
             Q = B @ B.T
             L, shift = shifted_cholesky(Q, prm.max_shifts)
             if L is None:
@@ -440,8 +446,11 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
             rhat = matvec(dy) - p
             gq = sla.cho_solve((L, True), rhat)
             u = B.T @ gq
-            W = sketch_matrix(n, w, sk, key, st.k)
-            v = np.sqrt(x * s) * (W @ u)
+            if prm.sketch == 1:
+                v = np.sqrt(x * s) * gaussian_apply(u, n, w, key, st.k)
+            else:
+                W = sketch_matrix(n, w, sk, key, st.k)
+                v = np.sqrt(x * s) * (W @ u)
         if keep:
             info.extra.update(B=B, Q=Q, L=L, pcg=res)
     ds = -(A.T @ dy) if prm.feasible else -rd - A.T @ dy

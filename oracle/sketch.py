@@ -95,3 +95,56 @@ def sketch_ADW(A: np.ndarray, d: np.ndarray, w: int, s: int, seed: int, k: int) 
     if sp.issparse(A):
         return np.asarray((W.T @ A.multiply(d[None, :]).tocsr().T).T.toarray())
     return np.asarray((W.T @ (A * d).T).T)
+
+
+# ---------------------------------------------------------------- Gaussian sketch
+
+# A Gaussian sketching matrix is the paper's experimental choice (Section 7; Section 6 notes
+# that it gives the same accuracy guarantees at a higher cost of forming A D W). Reading: W has
+# i.i.d. N(0, 1/w) entries, so E[W W^T] = I like the sparse embedding. Entry (j, c) (0-based,
+# row-major index e = j w + c) takes outputs 2e and 2e+1 of the SplitMix64 stream started at
+# K = mix64((seed ^ mix64(k)) + GAUSS_DOMAIN) and turns them into one normal deviate with the
+# Box-Muller transform (Box and Muller, 1958):
+#     u1 = ((h1 >> 11) + 1) 2^-53 in (0, 1],  u2 = (h2 >> 11) 2^-53 in [0, 1),
+#     z  = sqrt(-2 ln u1) cos(2 pi u2),       W[j, c] = z / sqrt(w).
+# The GPU library implements the same definition with its own code.
+GAUSS_DOMAIN = 0xD1B54A32D192ED03
+
+
+def gaussian_key(seed: int, k: int) -> int:
+    """Stream start state of the Gaussian sketch of IPM iteration k."""
+    return mix64_int(((seed ^ mix64_int(k)) + GAUSS_DOMAIN) & MASK64)
+
+
+def gaussian_rows(j0: int, j1: int, w: int, seed: int, k: int) -> np.ndarray:
+    """Rows j0..j1-1 of the Gaussian W (dense (j1 - j0) x w, FP64)."""
+    key = np.uint64(gaussian_key(seed, k))
+    e = (np.arange(j0, j1, dtype=np.uint64)[:, None] * np.uint64(w)
+         + np.arange(w, dtype=np.uint64)[None, :])
+    with np.errstate(over="ignore"):
+        h1 = mix64(key + (np.uint64(2) * e + np.uint64(1)) * np.uint64(PHI))
+        h2 = mix64(key + (np.uint64(2) * e + np.uint64(2)) * np.uint64(PHI))
+    u1 = ((h1 >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (h2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    return z / np.sqrt(w)
+
+
+def sketch_gaussian(A, d: np.ndarray, w: int, seed: int, k: int, chunk: int = 2048) -> np.ndarray:
+    """B = A diag(d) W for the Gaussian W of iteration k (m x w, FP64), W formed by row chunks."""
+    m, n = A.shape
+    B = np.zeros((m, w))
+    for j0 in range(0, n, chunk):
+        j1 = min(n, j0 + chunk)
+        Ad = A[:, j0:j1] @ sp.diags(d[j0:j1]) if sp.issparse(A) else A[:, j0:j1] * d[j0:j1]
+        B += np.asarray(Ad @ gaussian_rows(j0, j1, w, seed, k))
+    return B
+
+
+def gaussian_apply(u: np.ndarray, n: int, w: int, seed: int, k: int, chunk: int = 2048) -> np.ndarray:
+    """W u for the Gaussian W of iteration k (n-vector)."""
+    out = np.empty(n)
+    for j0 in range(0, n, chunk):
+        j1 = min(n, j0 + chunk)
+        out[j0:j1] = gaussian_rows(j0, j1, w, seed, k) @ u
+    return out

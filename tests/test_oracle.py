@@ -120,8 +120,9 @@ def test_first_direction_closed_form():
 
 # ------------------------------------------------------------------ Newton system identities
 
-@pytest.mark.parametrize("mode,maxit", [("exact", 500), ("sketch", 500), ("sketch", 1), ("sketch", 3)])
-def test_newton_system_identities(mode, maxit):
+@pytest.mark.parametrize("mode,maxit,kind", [("exact", 500, 0), ("sketch", 500, 0), ("sketch", 1, 0), ("sketch", 3, 0),
+                                             ("sketch", 1, 1), ("sketch", 500, 1)])
+def test_newton_system_identities(mode, maxit, kind):
     """A dx = -r_p, A^T dy + ds = -r_d, X ds + S dx = -XS1 + sigma mu 1 - v (eq. iip_3).
 
     Holds for any dy once v satisfies A S^-1 v = A D^2 A^T dy - p, so also for a
@@ -130,7 +131,7 @@ def test_newton_system_identities(mode, maxit):
     lp = lpgen.tiny_lp(8, 120, 4)
     x, y, s = interior_point(lp, seed=5)
     st = state_at(lp, x, y, s)
-    prm = ipm.Params(w=32, s=2, seed=9, maxit_pcg=maxit)
+    prm = ipm.Params(w=32, s=2, seed=9, maxit_pcg=maxit, sketch=kind)
     _, info = ipm.step(lp.A, lp.b, lp.c, st, prm, mode=mode, keep=True)
     e = info.extra
     A = lp.A
@@ -142,13 +143,15 @@ def test_newton_system_identities(mode, maxit):
     assert np.allclose(x * e["ds"] + s * e["dx"], rhs, atol=1e-11 * (1 + np.abs(rhs).max()))
 
 
-def test_v_invariant_and_norm_bound():
-    """A S^-1 v = M dy - p exactly (Lemma fullrankR) and ||v|| <= sqrt(3 n mu) ||f|| (Lemma v)."""
+@pytest.mark.parametrize("kind", [0, 1])
+def test_v_invariant_and_norm_bound(kind):
+    """A S^-1 v = M dy - p exactly (Lemma fullrankR) and ||v|| <= sqrt(3 n mu) ||f|| (Lemma v),
+    for the sparse embedding (kind 0) and the Gaussian sketch (kind 1)."""
     lp = lpgen.tiny_lp(10, 400, 5)
     x, y, s = interior_point(lp, seed=8)
     st = state_at(lp, x, y, s)
     # large sketch so the embedding condition holds (w.h.p.)
-    prm = ipm.Params(w=800, s=8, seed=2, maxit_pcg=2)
+    prm = ipm.Params(w=800, s=8, seed=2, maxit_pcg=2, sketch=kind)
     _, info = ipm.step(lp.A, lp.b, lp.c, st, prm, mode="sketch", keep=True)
     e = info.extra
     A = lp.A
