@@ -174,6 +174,26 @@ def vcorr_ablation(P, ctx):
     return out
 
 
+def sketch_comparison(P, ctx, prob, m, n, w, s):
+    """The sparse embedding (Section 2) against the Gaussian sketch (the experiments' choice,
+    Section 7) on the same LP: whole solves, and the Gaussian sketch's MFMA rate (2 m n w flop)."""
+    out = {}
+    for name, kind in (("sparse_embedding", 0), ("gaussian", 1)):
+        prm = P.Params(w=w, s=s, seed=0, sketch=kind)
+        timed_solve(P, ctx, prob, prm)
+        r = timed_solve(P, ctx, prob, prm, timing=True)
+        sk_ms, sk_n = r["kernels"]["sketch"]
+        r.pop("kernels")
+        r["sketch_ms"] = sk_ms / max(sk_n, 1)
+        if kind == 1:
+            r["sketch_tflops"] = 2.0 * m * n * w / (r["sketch_ms"] * 1e-3) / 1e12
+        out[name] = {k: r[k] for k in ("iterations", "iter_per_s", "cg_iterations", "seconds", "objective",
+                                       "sketch_ms") + (("sketch_tflops",) if kind == 1 else ())}
+        log(f"  {name}: {r['iterations']} IPM / {r['cg_iterations']} CG iterations, {r['iter_per_s']:.1f} it/s, "
+            f"sketch {r['sketch_ms']:.3f} ms")
+    return out
+
+
 def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
     """Plain FP64 form vs the mixed-precision form with the learned warm start on one held-out LP
     of an LP family, both solved to the same stop test; the network is trained first (untimed)
@@ -401,6 +421,8 @@ def main() -> int:
         out["algorithms"] = algorithm2_comparison(P, ctx, lp, prob, w, s)
         log("v-correction ablation on l1-SVM LPs")
         out["v_correction_ablation"] = vcorr_ablation(P, ctx)
+        log("sparse embedding vs Gaussian sketch")
+        out["sketches"] = sketch_comparison(P, ctx, prob, m, n, w, s)
     if args.forms != "none":
         out["forms"] = forms_comparison(P, ctx, args.forms, args.train_seeds, args.epochs)
     if not args.no_cpu_baseline:

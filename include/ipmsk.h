@@ -147,6 +147,11 @@ typedef struct {
                             eq. delxhat, and N(gamma) without its residual term (eq. neigh).
                             The residuals are still measured for the stop test.            */
     int32_t solver;      /* IPM_SOLVER_CG (the only value accepted)                         */
+    int32_t sketch;      /* IPM_SKETCH_SPARSE: the hashed sparse embedding (s nonzeros per
+                            row, Section 2). IPM_SKETCH_GAUSSIAN: W with N(0, 1/w) entries
+                            (the experiments' choice, Section 7), generated on the fly for Q
+                            and v; s is ignored; dense A only.                               */
+    int32_t reserved;    /* must be 0                                                       */
     uint64_t seed;       /* sketch seed                                                     */
 } ipm_params;
 
@@ -154,6 +159,8 @@ typedef struct {
 #define IPM_MIXED 1
 #define IPM_MIXED_F32ACC 2
 #define IPM_SOLVER_CG      0   /* preconditioned conjugate gradients (Algorithm 1, step 3)   */
+#define IPM_SKETCH_SPARSE   0  /* hashed sparse embedding, s signed nonzeros per row       */
+#define IPM_SKETCH_GAUSSIAN 1  /* i.i.d. N(0, 1/w) entries                                  */
 #define IPM_WARM_NONE 0
 #define IPM_WARM_PREV 1
 #define IPM_WARM_GIVEN 2
@@ -208,6 +215,17 @@ void ipm_params_default(ipm_params* p);
  * Errors: IPM_ERR_ARG if w < 1, s < 1, s > 8, s does not divide w, or pointers are null. */
 int ipm_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* d, uint64_t seed, int64_t k,
                int32_t w, int32_t s, int32_t out_dtype, void* B);
+
+/* Gaussian sketch B = A diag(d) W (the experiments' sketching matrix, Section 7), W with i.i.d.
+ * N(0, 1/w) entries that are generated, never stored: entry (j, c), e = j*w + c, takes outputs
+ * 2e and 2e+1 (h1, h2) of the SplitMix64 stream started at K = mix64((seed ^ mix64(k)) +
+ * 0xD1B54A32D192ED03), u1 = ((h1 >> 11) + 1) * 2^-53, u2 = (h2 >> 11) * 2^-53, and equals
+ * sqrt(-2 ln u1) cos(2 pi u2) / sqrt(w) (Box and Muller, 1958).
+ *   A    dense row-major m x n (CSR is rejected), any dtype;  d [device] n doubles
+ *   B    [device] m x w row-major FP64; overwritten. Accumulation is FP64 (MFMA).
+ * Errors: IPM_ERR_ARG for a CSR A, w < 1 or null pointers. */
+int ipm_sketch_gaussian(ipm_ctx* ctx, const ipm_matrix* A, const double* d, uint64_t seed, int64_t k,
+                        int32_t w, double* B);
 
 /* Preconditioner factor: Q = B B^T (eqn. pdprecond), Q = L L^T, and Linv = L^{-1}.
  *   B    [device] m x w row-major, b_dtype IPM_F64 or IPM_F32

@@ -18,7 +18,7 @@ from .native import (IPM_BF16, IPM_CONVERGED, IPM_CSR, IPM_F32, IPM_F64, IPM_MIX
                      IpmProblem, IpmState, IpmStepInfo)
 
 __all__ = ["IpmError", "Context", "Matrix", "SparseMatrix", "Problem", "State", "Params", "ipm_sketch",
-           "ipm_precond_factor", "ipm_pcg_solve", "ipm_step", "ipm_step_warm", "ipm_last_dy",
+           "ipm_sketch_gaussian", "ipm_precond_factor", "ipm_pcg_solve", "ipm_step", "ipm_step_warm", "ipm_last_dy",
            "ipm_normal_matvec", "solve", "IPM_OK", "IPM_CONVERGED", "IPM_F64", "IPM_F32", "IPM_BF16",
            "IPM_CSR", "IPM_PLAIN", "IPM_MIXED", "IPM_MIXED_F32ACC", "IPM_WARM_NONE", "IPM_WARM_PREV", "IPM_WARM_GIVEN"]
 
@@ -236,12 +236,14 @@ class Params:
     max_shifts: int = 3
     feasible: int = 0              # 1: Algorithm 2 from a strictly feasible state
     solver: int = 0                # IPM_SOLVER_CG
+    sketch: int = 0                # 0: sparse embedding; 1: Gaussian W
 
     def c(self) -> IpmParams:
         return IpmParams(self.sigma, self.gamma, self.theta, self.tol_pcg, self.gap_tol, self.min_step,
                          self.stag_ratio, self.w, self.s, self.maxit_pcg, self.stag_window, self.max_redraws,
                          self.vcorr, self.precision, self.warm_start, self.inner_tol, self.max_refine,
-                         self.max_shifts, self.feasible, self.solver, self.seed & ((1 << 64) - 1))
+                         self.max_shifts, self.feasible, self.solver, self.sketch, 0,
+                         self.seed & ((1 << 64) - 1))
 
 
 def ipm_normal_matvec(ctx: Context, A: Matrix, d2, v):
@@ -264,6 +266,16 @@ def ipm_sketch(ctx: Context, A: Matrix, d, seed: int, k: int, w: int, s: int, ou
     Ac = A.c()
     ctx.check(ctx.lib.ipm_sketch(ctx.h, ctypes.byref(Ac), _ptr(d), seed & ((1 << 64) - 1), k, w, s,
                                  _dtype_code(B), _ptr(B)))
+    return B
+
+
+def ipm_sketch_gaussian(ctx: Context, A, d, seed: int, k: int, w: int):
+    """B = A diag(d) W (FP64, m x w) for the Gaussian W of iteration k."""
+    torch = _torch()
+    _need_dev(d, "d", torch.float64)
+    B = torch.empty((A.m, w), dtype=torch.float64, device=d.device)
+    Ac = A.c()
+    ctx.check(ctx.lib.ipm_sketch_gaussian(ctx.h, ctypes.byref(Ac), _ptr(d), seed & ((1 << 64) - 1), k, w, _ptr(B)))
     return B
 
 

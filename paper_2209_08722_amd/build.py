@@ -18,7 +18,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libipmsk.so")
 ARCH = "gfx950"
 
-SOURCES = ["strip.hip", "sparse.hip", "dense.hip", "pcg.hip", "sketch.hip", "step.hip", "mlp.hip", "ipmsk.cpp"]
+SOURCES = ["strip.hip", "sparse.hip", "dense.hip", "gauss.hip", "pcg.hip", "sketch.hip", "step.hip", "mlp.hip",
+           "ipmsk.cpp"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

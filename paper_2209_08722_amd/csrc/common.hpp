@@ -27,6 +27,7 @@ extern thread_local LaunchTiming g_launch_timing;
     } while (0)
 
 constexpr uint64_t kPhi = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kGaussDomain = 0xD1B54A32D192ED03ull;   // offset of the Gaussian sketch's key
 
 // SplitMix64 output function (Steele, Lea, Flood 2014).
 __host__ __device__ inline uint64_t mix64(uint64_t z) {

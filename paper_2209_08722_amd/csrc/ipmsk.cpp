@@ -22,7 +22,7 @@ namespace {
 enum WsId {
     W_PART = 0, W_COLPART, W_RED, W_D2, W_RD, W_DS, W_DX, W_RP, W_P, W_DY, W_RHAT, W_G1, W_G2, W_U, W_B,
     W_L, W_X, W_XT, W_T, W_SCAL, W_PCG_VEC, W_PCG_RHO, W_PCG_CD, W_PCG_CI, W_STATUS, W_PART3, W_PARTMIN,
-    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_MLPF, W_MLPD, W_MLPI, W_WQ, W_COEF, W_COUNT
+    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_MLPF, W_MLPD, W_MLPI, W_WQ, W_COEF, W_GU, W_COUNT
 };
 
 struct TimedPair {
@@ -216,6 +216,31 @@ int do_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* dvals, int is_d2,
     }
     Timer t(ctx, IPM_KERNEL_SKETCH);
     HIPCHK(launch_sketch(A->dtype, A->val, m, A->n, A->ld, dvals, is_d2, hk, w, out_f64, B, sp, ctx->stream));
+    t.stop();
+    return IPM_OK;
+}
+
+// Gaussian sketch into an FP64 B (m x w): the MFMA kernel with split-K over n when the output
+// tiles alone cannot occupy every CU (one 8-wave block per CU); B is cleared first in that case.
+int do_sketch_gauss(ipm_ctx* ctx, const ipm_matrix* A, const double* dvals, int is_d2, uint64_t key, int w,
+                    double* B) {
+    if (A->layout != IPM_DENSE_ROWMAJOR) return fail(ctx, IPM_ERR_ARG, "the Gaussian sketch needs a dense A");
+    const int m = (int)A->m;
+    const int tiles = gauss_tiles(m, w);
+    int ks = 1;
+    double best = 0.0;
+    for (int c = 1; c <= 64 && (c == 1 || A->n / c >= 512); ++c) {
+        const int blocks = tiles * c, slots = ctx->num_cu;
+        const int rounds = (blocks + slots - 1) / slots;
+        const double eff = (double)blocks / ((double)rounds * slots);
+        if (eff > best + 0.02) {
+            best = eff;
+            ks = c;
+        }
+    }
+    if (ks > 1) HIPCHK(launch_fill(B, (int64_t)m * w, 0.0, ctx->stream));
+    Timer t(ctx, IPM_KERNEL_SKETCH);
+    HIPCHK(launch_sketch_gauss(A->dtype, m, A->n, w, A->val, A->ld, dvals, is_d2, key, B, ks, ctx->stream));
     t.stop();
     return IPM_OK;
 }
@@ -668,8 +693,11 @@ int check_params(ipm_ctx* ctx, const ipm_params* p, int64_t m) {
     if (p->maxit_pcg < 1 || p->maxit_pcg > 100000) return fail(ctx, IPM_ERR_ARG, "maxit_pcg out of range");
     if (p->stag_window < 1) return fail(ctx, IPM_ERR_ARG, "stag_window must be >= 1");
     if (p->max_redraws < 0 || p->max_redraws > 6) return fail(ctx, IPM_ERR_ARG, "max_redraws out of range");
+    if (p->sketch != IPM_SKETCH_SPARSE && p->sketch != IPM_SKETCH_GAUSSIAN)
+        return fail(ctx, IPM_ERR_ARG, "unknown sketch %d", p->sketch);
+    if (p->reserved != 0) return fail(ctx, IPM_ERR_ARG, "reserved must be 0");
     if (p->s < 1 || p->s > 8) return fail(ctx, IPM_ERR_ARG, "s must be in 1..8");
-    if (p->w < 1 || p->w % p->s != 0) return fail(ctx, IPM_ERR_ARG, "s must divide w");
+    if (p->w < 1 || (p->sketch == IPM_SKETCH_SPARSE && p->w % p->s != 0)) return fail(ctx, IPM_ERR_ARG, "s must divide w");
     if (p->w < m) return fail(ctx, IPM_ERR_ARG, "w (%d) must be >= m (%lld)", p->w, (long long)m);
     return check_solver_params(ctx, p);
 }
@@ -782,6 +810,17 @@ int ipm_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* d, uint64_t seed
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
     const HashKeys hk = make_keys(seed, k, w, s);
     CHK(do_sketch(ctx, A, d, 0, hk, w, out_dtype == IPM_F64, B));
+    return IPM_OK;
+}
+
+int ipm_sketch_gaussian(ipm_ctx* ctx, const ipm_matrix* A, const double* d, uint64_t seed, int64_t k, int32_t w,
+                        double* B) {
+    if (!ctx) return IPM_ERR_ARG;
+    CHK(check_matrix(ctx, A));
+    if (!d || !B) return fail(ctx, IPM_ERR_ARG, "null pointer");
+    if (w < 1) return fail(ctx, IPM_ERR_ARG, "need w >= 1");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    CHK(do_sketch_gauss(ctx, A, d, 0, gauss_key(seed, k), w, B));
     return IPM_OK;
 }
 
@@ -941,11 +980,14 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         ncand = 1;
     }
 
-    // Algorithm 1 with redraws of W: sketch, factor, CG. The mixed form keeps B in FP32.
+    // Algorithm 1 with redraws of W: sketch, factor, CG. The mixed form keeps a sparse sketch's B
+    // in FP32; the Gaussian sketch (an MFMA product) produces B in FP64 in every form.
+    const bool gauss = prm->sketch == IPM_SKETCH_GAUSSIAN;
+    const int b_f64 = (mixed && !gauss) ? 0 : 1;
     const int wmax = prm->w << prm->max_redraws;
     void* B = nullptr;
     double *Lw = nullptr, *X = nullptr;
-    if (mixed) {
+    if (!b_f64) {
         float* Bf = nullptr;
         CHK(ws(ctx, W_BF, (size_t)m * (size_t)wmax, &Bf));
         B = Bf;
@@ -957,6 +999,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
     CHK(ws(ctx, W_L, (size_t)m * m, &Lw));
     CHK(ws(ctx, W_X, (size_t)m * m, &X));
     HashKeys hk{};
+    uint64_t gkey = 0;
     int w_used = prm->w, s_used = prm->s;
     PcgOut po{};
     int attempts = 0;
@@ -967,9 +1010,11 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         s_used = a == 0 ? prm->s : (prm->s > 2 ? prm->s : 2);
         const uint64_t seed_a = a == 0 ? prm->seed : prm->seed + (uint64_t)a * 0x632BE59BD9B4E019ull;
         hk = make_keys(seed_a, state->k, w_used, s_used);
-        CHK(do_sketch(ctx, A, d2, 1, hk, w_used, mixed ? 0 : 1, B));
+        gkey = gauss_key(seed_a, state->k);
+        if (gauss) CHK(do_sketch_gauss(ctx, A, d2, 1, gkey, w_used, reinterpret_cast<double*>(B)));
+        else CHK(do_sketch(ctx, A, d2, 1, hk, w_used, b_f64, B));
         int64_t bad = -1;
-        CHK(do_factor(ctx, m, w_used, mixed ? 0 : 1, B, Lw, X, prm->max_shifts, &bad, &shift));
+        CHK(do_factor(ctx, m, w_used, b_f64, B, Lw, X, prm->max_shifts, &bad, &shift));
         if (bad >= 0) {
             if (a == prm->max_redraws) {
                 info->attempts = attempts;
@@ -1022,9 +1067,14 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         CHK(ws(ctx, W_XT, (size_t)m * m, &XT));   // written by do_pcg for this draw
         HIPCHK(launch_trigemv(X, m, 1, rhat, g1, st));
         HIPCHK(launch_trigemv(XT, m, 0, g1, g2, st));
-        HIPCHK(launch_btg(B, mixed ? 0 : 1, m, w_used, g2, u, st));
+        HIPCHK(launch_btg(B, b_f64, m, w_used, g2, u, st));
     }
-    HIPCHK(launch_dx(n, state->x, state->s, d2, ds, u, prm->vcorr, hk, scal, dx, part3, st));
+    double* wu = nullptr;   // W u for the Gaussian W (the sparse W is applied inside k_dx)
+    if (prm->vcorr && gauss) {
+        CHK(ws(ctx, W_GU, (size_t)n, &wu));
+        HIPCHK(launch_gauss_apply(n, w_used, gkey, u, wu, st));
+    }
+    HIPCHK(launch_dx(n, state->x, state->s, d2, ds, u, prm->vcorr, hk, wu, scal, dx, part3, st));
     HIPCHK(launch_fin_dx(part3, Gn, scal, st));
     HIPCHK(launch_roots(n, state->x, state->s, dx, ds, prm->gamma, scal, partmin, st));
     HIPCHK(launch_alpha(n, partmin, Gn, prm->gamma, prm->theta, prm->min_step, scal, st));

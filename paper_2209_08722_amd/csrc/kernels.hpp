@@ -98,8 +98,9 @@ hipError_t launch_sketch(int dtype, const void* A, int m, int64_t n, int64_t ld,
 hipError_t launch_btg(const void* B, int b_f64, int m, int w, const double* g, double* u, hipStream_t st);
 // dx and the sums a1 = x^T ds + s^T dx, a2 = dx^T ds, ||v||^2 as per-block partials [grid][3].
 int pointwise_blocks(int64_t n);
+// wu: (W u) precomputed (Gaussian W), or null to apply the hashed sparse W to u
 hipError_t launch_dx(int64_t n, const double* x, const double* s, const double* d2, const double* ds,
-                     const double* u, int vcorr, const HashKeys& hk, const double* scal, double* dx,
+                     const double* u, int vcorr, const HashKeys& hk, const double* wu, const double* scal, double* dx,
                      double* part3, hipStream_t st);
 
 // ---- dense FP64 linear algebra ----------------------------------------------------------------
@@ -117,6 +118,15 @@ hipError_t launch_dgemm_big(bool trans_b, bool lower_only, int M, int N, int K, 
                             hipStream_t st);
 hipError_t launch_sgram_f32_big(int m, int w, const float* B, double* C, int ksplit, hipStream_t st);
 hipError_t launch_fill_2d(double* C, int M, int N, int64_t ldc, hipStream_t st);   // M x N block of C <- 0
+
+// ---- Gaussian sketch (gauss.hip) ----
+uint64_t gauss_key(uint64_t seed, int64_t k);   // mix64((seed ^ mix64(k)) + kGaussDomain)
+int gauss_tiles(int m, int w);
+// B (m x w, FP64, cleared by the caller when ksplit > 1) = A diag(d) W, W generated from key
+hipError_t launch_sketch_gauss(int dtype, int m, int64_t n, int w, const void* A, int64_t lda, const double* dvals,
+                               int dvals_are_d2, uint64_t key, double* B, int ksplit, hipStream_t st);
+// t (n) = W u
+hipError_t launch_gauss_apply(int64_t n, int w, uint64_t key, const double* u, double* t, hipStream_t st);
 hipError_t launch_potrf_diag(double* Lw, int64_t ld, int k0, int kb, double* X, int64_t ldx, int* status,
                              hipStream_t st);
 hipError_t launch_transpose(const double* X, double* XT, int m, hipStream_t st);

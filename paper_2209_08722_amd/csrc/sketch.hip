@@ -164,15 +164,17 @@ __global__ __launch_bounds__(256) void k_btg(const BT* __restrict__ B, int m, in
 __global__ __launch_bounds__(256) void k_dx(int64_t n, const double* __restrict__ x, const double* __restrict__ s,
                                             const double* __restrict__ d2, const double* __restrict__ ds,
                                             const double* __restrict__ u, int vcorr, HashKeys hk,
-                                            const double* __restrict__ scal, double* __restrict__ dx,
-                                            double* __restrict__ part3) {
+                                            const double* __restrict__ wu, const double* __restrict__ scal,
+                                            double* __restrict__ dx, double* __restrict__ part3) {
     __shared__ double sh[4];
     const double smu = scal[SC_SMU];
     double a1 = 0.0, a2 = 0.0, v2 = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
         const double xj = x[j], sj = s[j], dsj = ds[j];
         double v = 0.0;
-        if (vcorr) {
+        if (vcorr && wu != nullptr) {
+            v = sqrt(xj * sj) * wu[j];   // (W u)_j computed beforehand (Gaussian W)
+        } else if (vcorr) {
             double acc = 0.0;
             for (int r = 0; r < hk.s; ++r) {
                 int bucket;
@@ -277,10 +279,10 @@ int pointwise_blocks(int64_t n) {
 }
 
 hipError_t launch_dx(int64_t n, const double* x, const double* s, const double* d2, const double* ds,
-                     const double* u, int vcorr, const HashKeys& hk, const double* scal, double* dx, double* part3,
-                     hipStream_t st) {
-    hipLaunchKernelGGL(k_dx, dim3(pointwise_blocks(n)), dim3(256), 0, st, n, x, s, d2, ds, u, vcorr, hk, scal, dx,
-                       part3);
+                     const double* u, int vcorr, const HashKeys& hk, const double* wu, const double* scal, double* dx,
+                     double* part3, hipStream_t st) {
+    hipLaunchKernelGGL(k_dx, dim3(pointwise_blocks(n)), dim3(256), 0, st, n, x, s, d2, ds, u, vcorr, hk, wu, scal,
+                       dx, part3);
     return hipGetLastError();
 }
 

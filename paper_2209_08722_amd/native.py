@@ -60,7 +60,7 @@ class IpmParams(ctypes.Structure):
                 ("w", c_int32), ("s", c_int32), ("maxit_pcg", c_int32), ("stag_window", c_int32),
                 ("max_redraws", c_int32), ("vcorr", c_int32), ("precision", c_int32), ("warm_start", c_int32),
                 ("inner_tol", c_double), ("max_refine", c_int32), ("max_shifts", c_int32), ("feasible", c_int32),
-                ("solver", c_int32), ("seed", c_uint64)]
+                ("solver", c_int32), ("sketch", c_int32), ("reserved", c_int32), ("seed", c_uint64)]
 
 
 class IpmPcgInfo(ctypes.Structure):
@@ -94,6 +94,8 @@ SIGNATURES = [
     ("ipm_params_default", None, [POINTER(IpmParams)]),
     ("ipm_sketch", c_int, [c_void_p, POINTER(IpmMatrix), c_void_p, c_uint64, c_int64, c_int32, c_int32,
                            c_int32, c_void_p]),
+    ("ipm_sketch_gaussian", c_int, [c_void_p, POINTER(IpmMatrix), c_void_p, c_uint64, c_int64, c_int32,
+                                    c_void_p]),
     ("ipm_precond_factor", c_int, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
                                    POINTER(c_int64)]),
     ("ipm_pcg_solve", c_int, [c_void_p, POINTER(IpmMatrix), c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
