@@ -81,6 +81,8 @@ class Params:
     max_shifts: int = 3
     feasible: bool = False      # Algorithm 2 instead of Algorithm 3
     sketch: int = 0             # 0: sparse embedding (Section 2); 1: Gaussian W (Section 7)
+    solver: int = 0             # 0: CG; 1: Chebyshev iteration after a CG probe (Section 3.2)
+    cheb_probe: int = 10
 
 
 @dataclass
@@ -181,6 +183,9 @@ class PCGResult:
     history: list            # ||L^{-1} r_j|| for j = 0..iters
     rho_star: float          # ||L^{-1} p||^2
     warm_used: bool = False
+    alphas: list = field(default_factory=list)   # CG step lengths alpha_j (for Lanczos estimates)
+    r: Optional[np.ndarray] = None               # recursive residual p - M dy at exit
+    interval: tuple = ()                         # Chebyshev: the eigenvalue interval used
 
 
 def pcg(matvec: Callable, L: np.ndarray, p: np.ndarray, tol: float, maxit: int,
@@ -237,11 +242,12 @@ def pcg(matvec: Callable, L: np.ndarray, p: np.ndarray, tol: float, maxit: int,
     thresh = tol * np.sqrt(rho_star)
     if np.sqrt(rho) <= thresh:
         rel = np.sqrt(rho / rho_star) if rho_star > 0 else 0.0
-        return PCGResult(dy, 0, OK, rel, hist, rho_star, warm_used)
+        return PCGResult(dy, 0, OK, rel, hist, rho_star, warm_used, [], r)
     z = ltsolve(wv)
     d = z.copy()
     status = PCG_MAXIT
     it = 0
+    alphas = []
     while it < maxit:
         q = matvec(d)
         dq = float(d @ q)
@@ -249,6 +255,7 @@ def pcg(matvec: Callable, L: np.ndarray, p: np.ndarray, tol: float, maxit: int,
             status = ERR_BREAKDOWN
             break
         alpha = rho / dq
+        alphas.append(alpha)
         dy = dy + alpha * d
         r = r - alpha * q
         wv = lsolve(r)
@@ -264,7 +271,87 @@ def pcg(matvec: Callable, L: np.ndarray, p: np.ndarray, tol: float, maxit: int,
         z = ltsolve(wv)
         d = z + (rho_new / rho) * d
         rho = rho_new
-    return PCGResult(dy, it, status, hist[-1] / np.sqrt(rho_star), hist, rho_star, warm_used)
+    return PCGResult(dy, it, status, hist[-1] / np.sqrt(rho_star), hist, rho_star, warm_used, alphas, r)
+
+
+def lanczos_ritz(alphas, history) -> np.ndarray:
+    """Eigenvalues of the Lanczos tridiagonal T_k that k CG steps build (the Ritz values of the
+    preconditioned matrix): with beta_j = rho_{j+1} / rho_j (rho_j = history[j]^2),
+    T[0,0] = 1/alpha_0, T[j,j] = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+    T[j,j+1] = T[j+1,j] = sqrt(beta_j)/alpha_j."""
+    k = len(alphas)
+    a = np.asarray(alphas, dtype=float)
+    h = np.asarray(history[:k + 1], dtype=float)
+    beta = (h[1:] / h[:-1]) ** 2                  # beta_0 .. beta_{k-1}
+    diag = 1.0 / a
+    diag[1:] += beta[:-1] / a[:-1]
+    off = np.sqrt(beta[:-1]) / a[:-1]
+    return sla.eigvalsh_tridiagonal(diag, off)
+
+
+def chebyshev(matvec: Callable, L: np.ndarray, p: np.ndarray, lo: float, hi: float, tol: float, maxit: int,
+              dy: np.ndarray, r: np.ndarray, rho_star: float, history: list, start_it: int = 0,
+              stag_window: int = 10, stag_ratio: float = 0.99):
+    """Preconditioned Chebyshev iteration (Section 3.2) for the eigenvalue interval [lo, hi] of
+    Q^{-1} M, continuing from dy with residual r = p - M dy; the three-term recurrence in
+    correction form, theta = (hi + lo)/2, delta = (hi - lo)/2, s = delta/theta:
+        omega_1 = 1, omega_2 = 1 / (1 - s^2/2), omega_{t+1} = 1 / (1 - s^2 omega_t / 4),
+        dx_t = (omega_{t+1}/theta) Q^{-1} r_t + (omega_{t+1} - 1) dx_{t-1},
+        dy += dx_t, r -= M dx_t.
+    No inner products enter the recurrence; ||L^{-1} r|| is only measured for the stop test.
+    Returns (dy, r, iterations, status, history)."""
+    theta = 0.5 * (hi + lo)
+    delta = 0.5 * (hi - lo)
+    s2 = (delta / theta) ** 2
+    thresh = tol * np.sqrt(rho_star)
+    hist = list(history)
+    dx = np.zeros_like(dy)
+    omega = 1.0
+    t = 0
+    status = PCG_MAXIT
+    while True:
+        wv = sla.solve_triangular(L, r, lower=True)
+        res = float(np.sqrt(wv @ wv))
+        it = start_it + t
+        if t > 0:
+            hist.append(res)
+        if res <= thresh:
+            status = OK
+            break
+        if t > 0 and it >= stag_window and hist[-1] > stag_ratio * hist[-1 - stag_window]:
+            status = PCG_STAGNATED
+            break
+        if it >= maxit:
+            status = PCG_MAXIT
+            break
+        z = sla.solve_triangular(L, wv, lower=True, trans="T")
+        omega = 1.0 if t == 0 else (1.0 / (1.0 - 0.5 * s2) if t == 1 else 1.0 / (1.0 - 0.25 * s2 * omega))
+        dx = (omega / theta) * z + (omega - 1.0) * dx
+        dy = dy + dx
+        r = r - matvec(dx)
+        t += 1
+    return dy, r, start_it + t, status, hist
+
+
+def pcg_chebyshev(matvec: Callable, L: np.ndarray, p: np.ndarray, tol: float, maxit: int,
+                  dy0: Optional[np.ndarray] = None, probe: int = 10, lo_factor: float = 0.5,
+                  hi_factor: float = 1.1, stag_window: int = 10, stag_ratio: float = 0.99) -> PCGResult:
+    """Chebyshev iteration in place of CG (Section 3.2). Its eigenvalue interval comes from
+    Lemma cond3 when the sketch meets eq. pdcond1; at practical sketch sizes it is estimated:
+    ``probe`` CG steps run first and the extreme Ritz values theta_min, theta_max of their
+    Lanczos tridiagonal give [lo_factor theta_min, hi_factor theta_max] (theta_max approaches
+    lambda_max from below, theta_min overestimates lambda_min, hence the margins). Chebyshev
+    then continues from the CG iterate."""
+    res = pcg(matvec, L, p, tol, min(probe, maxit), dy0=dy0, stag_window=stag_window, stag_ratio=stag_ratio)
+    if res.status != PCG_MAXIT or res.iters < probe or res.iters >= maxit:
+        return res
+    ritz = lanczos_ritz(res.alphas, res.history)
+    lo, hi = lo_factor * float(ritz[0]), hi_factor * float(ritz[-1])
+    dy, r, it, status, hist = chebyshev(matvec, L, p, lo, hi, tol, maxit, res.dy, res.r, res.rho_star,
+                                        res.history, start_it=res.iters, stag_window=stag_window,
+                                        stag_ratio=stag_ratio)
+    return PCGResult(dy, it, status, hist[-1] / np.sqrt(res.rho_star), hist, res.rho_star, res.warm_used,
+                     res.alphas, r, (lo, hi))
 
 
 # ---------------------------------------------------------------- step lengths
@@ -432,8 +519,12 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
                     info.extra.update(attempts=attempt + 1)
                     return st, info
                 continue
-            res = pcg(matvec, L, p, prm.tol_pcg, prm.maxit_pcg, dy0=dy0,
-                      stag_window=prm.stag_window, stag_ratio=prm.stag_ratio)
+            if prm.solver == 1:
+                res = pcg_chebyshev(matvec, L, p, prm.tol_pcg, prm.maxit_pcg, dy0=dy0, probe=prm.cheb_probe,
+                                    stag_window=prm.stag_window, stag_ratio=prm.stag_ratio)
+            else:
+                res = pcg(matvec, L, p, prm.tol_pcg, prm.maxit_pcg, dy0=dy0,
+                          stag_window=prm.stag_window, stag_ratio=prm.stag_ratio)
             if res.status in (OK, ERR_BREAKDOWN):
                 break
         info.extra.update(attempts=attempt + 1, w_used=w, s_used=sk, shift=shift)
