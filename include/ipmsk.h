@@ -146,7 +146,8 @@ typedef struct {
                             sigma mu A S^-1 1 (eqn. pdef), ds = -A^T dy (eq. dels), dx as in
                             eq. delxhat, and N(gamma) without its residual term (eq. neigh).
                             The residuals are still measured for the stop test.            */
-    int32_t solver;      /* IPM_SOLVER_CG (the only value accepted)                         */
+    int32_t solver;      /* IPM_SOLVER_CG | IPM_SOLVER_CHEBYSHEV (plain and IPM_MIXED forms;
+                            the refinement form's inner solves stay CG)                      */
     int32_t sketch;      /* IPM_SKETCH_SPARSE: the hashed sparse embedding (s nonzeros per
                             row, Section 2). IPM_SKETCH_GAUSSIAN: W with N(0, 1/w) entries
                             (the experiments' choice, Section 7), generated on the fly for Q
@@ -159,6 +160,9 @@ typedef struct {
 #define IPM_MIXED 1
 #define IPM_MIXED_F32ACC 2
 #define IPM_SOLVER_CG      0   /* preconditioned conjugate gradients (Algorithm 1, step 3)   */
+#define IPM_SOLVER_CHEBYSHEV 1 /* Chebyshev iteration (Section 3.2) after a 10-step CG probe:
+                                  the probe's Lanczos Ritz values theta_min, theta_max give the
+                                  interval [0.5 theta_min, 1.1 theta_max]; same stop test     */
 #define IPM_SKETCH_SPARSE   0  /* hashed sparse embedding, s signed nonzeros per row       */
 #define IPM_SKETCH_GAUSSIAN 1  /* i.i.d. N(0, 1/w) entries                                  */
 #define IPM_WARM_NONE 0

@@ -235,7 +235,7 @@ class Params:
     max_refine: int = 12
     max_shifts: int = 3
     feasible: int = 0              # 1: Algorithm 2 from a strictly feasible state
-    solver: int = 0                # IPM_SOLVER_CG
+    solver: int = 0                # 0: CG; 1: Chebyshev after a CG probe
     sketch: int = 0                # 0: sparse embedding; 1: Gaussian W
 
     def c(self) -> IpmParams:

@@ -459,6 +459,7 @@ int resid_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double
 struct PcgOut {
     int iters, status, warm_used, rounds;
     double relres, rho_star;
+    double cheb_lo = 0.0, cheb_hi = 0.0;   // Chebyshev interval used (0: CG only)
 };
 
 struct PcgCfg {
@@ -467,7 +468,47 @@ struct PcgCfg {
     int acc64;          // matvec accumulation: 1 FP64, 0 FP32 (low-precision storage only)
     bool xt_ready;      // W_XT already holds X^T
     int* last_iters;    // first batch size hint, updated with the count of this solve
+    int cheb_probe = 0; // > 0: Chebyshev iteration after this many CG steps
 };
+
+// Chebyshev interval from the CG probe (Section 3.2 needs bounds on the spectrum of the
+// preconditioned matrix; at practical sketch sizes they are estimated): the extreme Ritz values
+// of the Lanczos tridiagonal the probe's CG steps build, widened by these factors.
+constexpr int kChebProbe = 10;
+constexpr double kChebLo = 0.5, kChebHi = 1.1;
+
+// Smallest and largest eigenvalue of the symmetric tridiagonal (diag d[0..k-1], off-diagonal
+// e[0..k-2]) by bisection on the Sturm sequence count, from the Gershgorin interval.
+void tridiag_extremes(const double* d, const double* e, int k, double* lo, double* hi) {
+    double gl = d[0], gu = d[0];
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(e[i]) : 0.0);
+        gl = std::fmin(gl, d[i] - r);
+        gu = std::fmax(gu, d[i] + r);
+    }
+    auto below = [&](double x) {   // number of eigenvalues < x
+        int c = 0;
+        double q = d[0] - x;
+        if (q < 0) ++c;
+        for (int i = 1; i < k; ++i) {
+            if (q == 0.0) q = 1e-300;
+            q = d[i] - x - e[i - 1] * e[i - 1] / q;
+            if (q < 0) ++c;
+        }
+        return c;
+    };
+    auto kth = [&](int target) {   // smallest x with below(x) >= target
+        double a = gl, b = gu;
+        for (int it = 0; it < 200 && b - a > 1e-15 * std::fmax(std::fabs(a), std::fabs(b)); ++it) {
+            const double mid = 0.5 * (a + b);
+            if (below(mid) >= target) b = mid;
+            else a = mid;
+        }
+        return 0.5 * (a + b);
+    };
+    *lo = kth(1);
+    *hi = kth(k);
+}
 
 // Initial iterate from ncand (1 or 2) candidate vectors cand[0:m], cand[m:2m]: their
 // M-norm-optimal combination into dy_out, M dy_out into q_out and, if r_out is given,
@@ -483,6 +524,84 @@ int warm_combination(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const 
     }
     HIPCHK(launch_warm_galerkin(m, ncand, cand, ncand > 1 ? cand + m : nullptr, p, q_out, q2, dy_out, q_out, r_out,
                                 ctx->stream));
+    return IPM_OK;
+}
+
+// Chebyshev iteration (Section 3.2) continuing the CG probe held in b (iterate dy[k & 1],
+// residual r[k & 1] after k = out->iters steps): the interval comes from the probe's Lanczos
+// tridiagonal; the three-term recurrence in correction form (theta, delta the interval's centre
+// and half-width, s = delta / theta; omega_1 = 1, omega_2 = 1 / (1 - s^2 / 2),
+// omega_{t+1} = 1 / (1 - s^2 omega_t / 4); dx_t = (omega_{t+1} / theta) Q^{-1} r_t +
+// (omega_{t+1} - 1) dx_{t-1}) has host-computed coefficients, so no inner products enter it and
+// whole batches are queued; the stop test is the CG's, on ||X r|| (device flag).
+int chebyshev_stage(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, PcgBufs b, const PcgCfg& cfg,
+                    double* dy_out, PcgOut* out) {
+    hipStream_t st = ctx->stream;
+    const int m = b.m, k = out->iters;
+    double* hd = reinterpret_cast<double*>(ctx->pinned);
+    static_assert(kChebProbe + 1 <= 32, "probe history must fit the pinned staging");
+    HIPCHK(hipMemcpyAsync(hd, b.cd + PD_HIST, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hd + 32, b.ahist, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double dg[kChebProbe], of[kChebProbe];
+    for (int i = 0; i < k; ++i) {
+        const double beta_prev = i > 0 ? (hd[i] / hd[i - 1]) * (hd[i] / hd[i - 1]) : 0.0;
+        dg[i] = 1.0 / hd[32 + i] + (i > 0 ? beta_prev / hd[32 + i - 1] : 0.0);
+        if (i + 1 < k) of[i] = (hd[i + 1] / hd[i]) / hd[32 + i];   // sqrt(beta_i) / alpha_i
+    }
+    double rlo = 0.0, rhi = 0.0;
+    tridiag_extremes(dg, of, k, &rlo, &rhi);
+    const double lo = kChebLo * rlo, hi = kChebHi * rhi;
+    if (!(lo > 0.0) || !(hi > lo) || !is_finite(hi)) return IPM_OK;   // keep the CG result
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), s2 = (delta / theta) * (delta / theta);
+    const int par = k & 1;
+    double* dy = b.dy[par];
+    double* r = b.r[par];
+    double* dx = b.dv;
+    double* g = b.wv;
+    b.maxit = cfg.maxit;
+    HIPCHK(launch_fill(dx, m, 0.0, st));
+    HIPCHK(launch_fill_i32(b.ci, 2, 0, st));   // PI_DONE, PI_STATUS
+    // first batch: the count the residual bound 2 rho^t (rho = (sqrt(kappa)-1)/(sqrt(kappa)+1))
+    // predicts for the remaining reduction, then short batches
+    const double kap = hi / lo, rc = (std::sqrt(kap) - 1.0) / (std::sqrt(kap) + 1.0);
+    const double need = std::log(2.0 * hd[k] / (cfg.tol * std::sqrt(out->rho_star) + 1e-300)) / std::log(1.0 / rc);
+    int batch = (int)std::ceil(need) + 1;
+    if (batch < 4) batch = 4;
+    const int* done = b.ci + PI_DONE;
+    int t = 0;
+    double omega = 1.0;
+    int* hi_ = reinterpret_cast<int*>(ctx->pinned);
+    for (;;) {
+        for (int u = 0; u < batch && k + t <= cfg.maxit; ++u, ++t) {
+            omega = t == 0 ? 1.0 : (t == 1 ? 1.0 / (1.0 - 0.5 * s2) : 1.0 / (1.0 - 0.25 * s2 * omega));
+            HIPCHK(launch_cheb1(b, r, g, st));
+            HIPCHK(launch_cheb2(b, g, dx, dy, omega / theta, omega - 1.0, k + t, t, st));
+            StripCall c{};
+            c.kind = STRIP_MATVEC;
+            c.acc64 = cfg.acc64;
+            c.post = POST_SUBR;
+            c.vec0 = dx;
+            c.d2 = d2;
+            c.out0 = r;
+            c.done = done;
+            CHK(run_pass(ctx, A, c, cfg.acc64 || A->dtype == IPM_F64 ? IPM_KERNEL_MATVEC : IPM_KERNEL_MATVEC32, k + t));
+        }
+        HIPCHK(hipMemcpyAsync(hi_, b.ci, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hi_[PI_DONE] || k + t > cfg.maxit) break;
+        batch = 8;
+    }
+    const int iters = hi_[PI_DONE] ? hi_[PI_ITERS] : cfg.maxit;
+    const int status = hi_[PI_DONE] ? hi_[PI_STATUS] : IPM_PCG_MAXIT;
+    HIPCHK(hipMemcpyAsync(hd, b.cd + PD_HIST + iters, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(dy_out, dy, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    out->iters = iters;
+    out->status = status;
+    out->relres = out->rho_star > 0.0 ? hd[0] / std::sqrt(out->rho_star) : 0.0;
+    out->cheb_lo = lo;
+    out->cheb_hi = hi;
     return IPM_OK;
 }
 
@@ -502,7 +621,9 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     CHK(ws(ctx, W_PCG_VEC, (size_t)8 * m, &vec));
     const int gb = gemv_blocks(m);
     CHK(ws(ctx, W_PCG_RHO, (size_t)2 * gb, &rho));
-    CHK(ws(ctx, W_PCG_CD, (size_t)PD_HIST + cfg.maxit + 2, &cd));
+    CHK(ws(ctx, W_PCG_CD, (size_t)PD_HIST + 2 * (cfg.maxit + 2), &cd));
+    const bool cheb = cfg.cheb_probe > 0 && cfg.cheb_probe < cfg.maxit;
+    const int cg_maxit = cheb ? cfg.cheb_probe : cfg.maxit;
     CHK(ws(ctx, W_PCG_CI, PI_COUNT, &ci));
     CHK(ws(ctx, W_INFO, 8, &info));
     PcgBufs b{};
@@ -525,7 +646,8 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     b.tol = cfg.tol;
     b.stag_ratio = prm->stag_ratio;
     b.stag_window = prm->stag_window;
-    b.maxit = cfg.maxit;
+    b.maxit = cg_maxit;
+    b.ahist = cheb ? cd + PD_HIST + cfg.maxit + 2 : nullptr;
     HIPCHK(launch_fill_i32(ci, PI_COUNT, 0, st));
     if (warm) CHK(warm_combination(ctx, A, d2, p, cand, ncand, cfg.acc64, dy_out, b.q, nullptr));
     HIPCHK(launch_pcg_init1(b, warm, st));
@@ -536,10 +658,10 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     // iterations); later batches are short so that few no-op launches follow the stop. Every
     // batch ends with the finish kernel (it only reads the CG state), so the batch whose
     // readback shows the stop already carries the result: one synchronization per batch.
-    int batch = *cfg.last_iters > 4 ? *cfg.last_iters : 4;
+    int batch = cheb ? cg_maxit : (*cfg.last_iters > 4 ? *cfg.last_iters : 4);
     const int* done = ci + PI_DONE;
     for (;;) {
-        for (int t = 0; t < batch && j < cfg.maxit; ++t, ++j) {
+        for (int t = 0; t < batch && j < cg_maxit; ++t, ++j) {
             CHK(matvec_pass(ctx, A, d2, b.dv, b.q, done, j, cfg.acc64));
             HIPCHK(launch_pcg_gemv1(b, j, st));
             HIPCHK(launch_pcg_gemv2(b, j, st));
@@ -547,7 +669,7 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
         HIPCHK(launch_pcg_finish(b, dy_out, info, st));
         HIPCHK(hipMemcpyAsync(hd, info, sizeof(double) * 6, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (hd[5] != 0.0 || j >= cfg.maxit) break;
+        if (hd[5] != 0.0 || j >= cg_maxit) break;
         batch = 4;
     }
     out->iters = (int)hd[0];
@@ -556,6 +678,8 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     out->relres = hd[3];
     out->rho_star = hd[4];
     out->rounds = 1;
+    if (cheb && out->status == IPM_PCG_MAXIT && out->iters == cg_maxit)
+        CHK(chebyshev_stage(ctx, A, d2, b, cfg, dy_out, out));
     *cfg.last_iters = out->iters;
     resolve_timing(ctx, IPM_KERNEL_MATVEC, out->iters);
     resolve_timing(ctx, IPM_KERNEL_MATVEC32, out->iters);
@@ -677,7 +801,8 @@ int check_solver_params(ipm_ctx* ctx, const ipm_params* p) {
     if (p->max_refine < 1 || p->max_refine > 1000) return fail(ctx, IPM_ERR_ARG, "max_refine out of range");
     if (p->max_shifts < 0 || p->max_shifts > 8) return fail(ctx, IPM_ERR_ARG, "max_shifts out of range");
     if (p->feasible != 0 && p->feasible != 1) return fail(ctx, IPM_ERR_ARG, "feasible must be 0 or 1");
-    if (p->solver != IPM_SOLVER_CG) return fail(ctx, IPM_ERR_ARG, "unknown solver %d", p->solver);
+    if (p->solver != IPM_SOLVER_CG && p->solver != IPM_SOLVER_CHEBYSHEV)
+        return fail(ctx, IPM_ERR_ARG, "unknown solver %d", p->solver);
     return IPM_OK;
 }
 
@@ -861,6 +986,7 @@ int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const dou
         CHK(do_pcg_mixed(ctx, A, d2, Linv, p, dy, dy0, dy0 ? 1 : 0, params, &o));
     } else {
         PcgCfg cfg{params->tol_pcg, params->maxit_pcg, 1, false, &ctx->last_pcg_iters};
+        cfg.cheb_probe = params->solver == IPM_SOLVER_CHEBYSHEV ? kChebProbe : 0;
         CHK(do_pcg(ctx, A, d2, Linv, p, dy, warm ? dy : nullptr, warm ? 1 : 0, params, cfg, &o));
     }
     if (info) {
@@ -1027,6 +1153,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
             CHK(do_pcg_mixed(ctx, A, d2, X, p, dyv, dy0, ncand, prm, &po));
         } else {
             PcgCfg cfg{prm->tol_pcg, prm->maxit_pcg, 1, false, &ctx->last_pcg_iters};
+            cfg.cheb_probe = prm->solver == IPM_SOLVER_CHEBYSHEV ? kChebProbe : 0;
             CHK(do_pcg(ctx, A, d2, X, p, dyv, dy0, ncand, prm, cfg, &po));
         }
         if (po.status == IPM_ERR_BREAKDOWN) {

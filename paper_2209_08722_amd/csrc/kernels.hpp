@@ -13,7 +13,7 @@ enum Scalar {
 };
 
 // Post-processing of the row reduction of strip-pass partials.
-enum RowPost { POST_PLAIN = 0, POST_MATVEC = 1, POST_RESID = 2, POST_RHAT = 3, POST_RESP = 4 };
+enum RowPost { POST_PLAIN = 0, POST_MATVEC = 1, POST_RESID = 2, POST_RHAT = 3, POST_RESP = 4, POST_SUBR = 5 };
 
 // Kinds of single-pass strip kernels over row-major A.
 enum StripKind { STRIP_MATVEC = 0, STRIP_RESID = 1, STRIP_DIR = 2 };
@@ -158,9 +158,16 @@ struct PcgBufs {
     double stag_ratio;
     int stag_window;
     int maxit;
+    double* ahist;        // CG step lengths alpha_j (Lanczos estimate for Chebyshev), or null
 };
 int gemv_blocks(int m);
 hipError_t launch_pcg_init1(const PcgBufs& b, int warm, hipStream_t st);
+// Chebyshev iteration (Section 3.2), continuing CG's iterate: g = X r with per-block ||g||^2
+// (cheb1), then the stop test at total iteration jt, z = X^T g, dx = c1 z + c2 dx, dy += dx
+// (cheb2); the matvec pass then subtracts M dx from r (POST_SUBR).
+hipError_t launch_cheb1(const PcgBufs& b, const double* r, double* g, hipStream_t st);
+hipError_t launch_cheb2(const PcgBufs& b, const double* g, double* dx, double* dy, double c1, double c2, int jt,
+                        int t, hipStream_t st);
 hipError_t launch_pcg_init2(const PcgBufs& b, int warm, const double* dy_in, hipStream_t st);
 hipError_t launch_pcg_gemv1(const PcgBufs& b, int j, hipStream_t st);
 hipError_t launch_pcg_gemv2(const PcgBufs& b, int j, hipStream_t st);

@@ -205,6 +205,7 @@ __global__ __launch_bounds__(GNT) void k_pcg_gemv1(PcgBufs b, int j) {
         return;
     }
     const double alpha = b.cd[PD_RHO0 + par] / dq;
+    if (b.ahist != nullptr && blockIdx.x == 0 && tid == 0) b.ahist[j] = alpha;
     const double* __restrict__ rin = b.r[par];
     for (int l = tid; l < m; l += GNT) {
         const double rn = rin[l] - alpha * b.q[l];
@@ -261,6 +262,72 @@ __global__ __launch_bounds__(GNT) void k_pcg_gemv2(PcgBufs b, int j) {
             b.ci[PI_STATUS] = status;
             b.ci[PI_ITERS] = it;
             b.ci[PI_DONE] = 1;
+        }
+    }
+}
+
+// Chebyshev, first GEMV: g = X r, per-block ||g||^2 into rho_part.
+__global__ __launch_bounds__(GNT) void k_cheb1(PcgBufs b, const double* __restrict__ r, double* __restrict__ g) {
+    if (b.ci[PI_DONE]) return;
+    extern __shared__ double xs[];   // [m]
+    __shared__ double sh[GNW];
+    const int m = b.m, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int row0 = blockIdx.x * GNW + wid;
+    double mv[PRE];
+    preload_lower(b.X, m, row0, lane, mv);
+    for (int l = tid; l < m; l += GNT) xs[l] = r[l];
+    __syncthreads();
+    double s = 0.0;
+    for (int row = row0; row < m; row += gridDim.x * GNW) {
+        if (row != row0) preload_lower(b.X, m, row, lane, mv);
+        const double w = finish_lower(b.X, m, row, xs, lane, mv);
+        if (lane == 0) { g[row] = w; s += w * w; }
+    }
+    const double tt = block_sum(s, sh);
+    if (tid == 0) b.rho_part[blockIdx.x] = tt;
+}
+
+// Chebyshev, second GEMV: every block evaluates the stop test from the partials (so all blocks
+// take the same decision); unless it stops, z = X^T g, dx = c1 z + c2 dx and dy += dx for the
+// block's rows. jt is the total iteration count (CG probe + Chebyshev steps), t the Chebyshev
+// step (the residual of step 0 is CG's last one, already in the history).
+__global__ __launch_bounds__(GNT) void k_cheb2(PcgBufs b, const double* __restrict__ g, double* __restrict__ dx,
+                                               double* __restrict__ dy, double c1, double c2, int jt, int t) {
+    if (b.ci[PI_DONE]) return;
+    extern __shared__ double xs[];   // [m]
+    __shared__ double sh[GNW];
+    const int m = b.m, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int row0 = blockIdx.x * GNW + wid;
+    double mv[PRE];
+    preload_upper(b.XT, m, row0, lane, mv);
+    const double res = sqrt(sum_partials(b.rho_part, b.n_rho, 1, sh));
+    double* hist = b.cd + PD_HIST;
+    int stop = 0, status = 0;
+    if (res <= b.tol * sqrt(b.cd[PD_RHOSTAR])) {
+        stop = 1;
+    } else if (t > 0 && jt >= b.stag_window && res > b.stag_ratio * hist[jt - b.stag_window]) {
+        stop = 1; status = 3;   // IPM_PCG_STAGNATED
+    } else if (jt >= b.maxit) {
+        stop = 1; status = 2;   // IPM_PCG_MAXIT
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        if (t > 0) hist[jt] = res;
+        if (stop) {
+            b.ci[PI_STATUS] = status;
+            b.ci[PI_ITERS] = jt;
+            b.ci[PI_DONE] = 1;
+        }
+    }
+    if (stop) return;
+    for (int l = tid; l < m; l += GNT) xs[l] = g[l];
+    __syncthreads();
+    for (int row = row0; row < m; row += gridDim.x * GNW) {
+        if (row != row0) preload_upper(b.XT, m, row, lane, mv);
+        const double z = finish_upper(b.XT, m, row, xs, lane, mv);
+        if (lane == 0) {
+            const double d = c1 * z + c2 * dx[row];
+            dx[row] = d;
+            dy[row] += d;
         }
     }
 }
@@ -323,6 +390,18 @@ hipError_t launch_pcg_gemv1(const PcgBufs& b, int j, hipStream_t st) {
 
 hipError_t launch_pcg_gemv2(const PcgBufs& b, int j, hipStream_t st) {
     hipLaunchKernelGGL(k_pcg_gemv2, dim3(gemv_blocks(b.m)), dim3(GNT), sizeof(double) * b.m, st, b, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_cheb1(const PcgBufs& b, const double* r, double* g, hipStream_t st) {
+    hipLaunchKernelGGL(k_cheb1, dim3(gemv_blocks(b.m)), dim3(GNT), sizeof(double) * b.m, st, b, r, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_cheb2(const PcgBufs& b, const double* g, double* dx, double* dy, double c1, double c2, int jt,
+                        int t, hipStream_t st) {
+    hipLaunchKernelGGL(k_cheb2, dim3(gemv_blocks(b.m)), dim3(GNT), sizeof(double) * b.m, st, b, g, dx, dy, c1, c2,
+                       jt, t);
     return hipGetLastError();
 }
 

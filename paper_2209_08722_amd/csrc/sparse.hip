@@ -82,6 +82,7 @@ __global__ __launch_bounds__(RNT_S) void k_csr_rows(StripCall a, int nacc, int n
                 }
                 case POST_RHAT: a.out0[i] = t0 - a.pvec[i]; break;
                 case POST_RESP: a.out0[i] = a.pvec[i] - t0; break;
+                case POST_SUBR: a.out0[i] -= t0; break;   // r -= M dx (Chebyshev)
                 default: break;
             }
         }
