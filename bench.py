@@ -194,6 +194,24 @@ def sketch_comparison(P, ctx, prob, m, n, w, s):
     return out
 
 
+def solver_comparison(P, ctx, prob, w, s):
+    """CG against the Chebyshev iteration (Section 3.2; eigenvalue interval from a 10-step CG
+    probe) as the inner solver on the same LP: whole solves, inner iterations and the time per
+    inner iteration (solve time over inner iterations, an upper bound that includes the sketch,
+    factorization and step work)."""
+    out = {}
+    for name, kind in (("cg", 0), ("chebyshev", 1)):
+        prm = P.Params(w=w, s=s, seed=0, solver=kind)
+        timed_solve(P, ctx, prob, prm)
+        r = timed_solve(P, ctx, prob, prm)
+        r["us_per_inner_iteration"] = 1e6 * r["seconds"] / max(r["cg_iterations"], 1)
+        out[name] = {k: r[k] for k in ("converged", "iterations", "iter_per_s", "cg_iterations",
+                                       "max_cg_iterations", "us_per_inner_iteration", "seconds", "objective")}
+        log(f"  {name}: {r['iterations']} IPM / {r['cg_iterations']} inner iterations, {r['iter_per_s']:.1f} it/s, "
+            f"{r['us_per_inner_iteration']:.1f} us per inner iteration")
+    return out
+
+
 def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
     """Plain FP64 form vs the mixed-precision form with the learned warm start on one held-out LP
     of an LP family, both solved to the same stop test; the network is trained first (untimed)
@@ -423,6 +441,8 @@ def main() -> int:
         out["v_correction_ablation"] = vcorr_ablation(P, ctx)
         log("sparse embedding vs Gaussian sketch")
         out["sketches"] = sketch_comparison(P, ctx, prob, m, n, w, s)
+        log("CG vs Chebyshev inner solver")
+        out["inner_solvers"] = solver_comparison(P, ctx, prob, w, s)
     if args.forms != "none":
         out["forms"] = forms_comparison(P, ctx, args.forms, args.train_seeds, args.epochs)
     if not args.no_cpu_baseline:

@@ -49,6 +49,7 @@ struct ipm_ctx {
     std::vector<hipEvent_t> pool;
     int last_pcg_iters = 8;    // size of the first batch of queued CG iterations
     int last_inner_iters = 8;  // the same for the inner solves of the mixed form
+    int last_cheb_steps = 0;   // Chebyshev steps of the previous solve (first batch after the probe)
     int64_t prev_m = 0;        // length of the accepted dy kept in W_PREV (0: none)
 };
 
@@ -562,11 +563,14 @@ int chebyshev_stage(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, PcgBufs
     b.maxit = cfg.maxit;
     HIPCHK(launch_fill(dx, m, 0.0, st));
     HIPCHK(launch_fill_i32(b.ci, 2, 0, st));   // PI_DONE, PI_STATUS
-    // first batch: the count the residual bound 2 rho^t (rho = (sqrt(kappa)-1)/(sqrt(kappa)+1))
-    // predicts for the remaining reduction, then short batches
+    // first batch: the previous solve's step count, capped by the count the residual bound
+    // 2 rho^t (rho = (sqrt(kappa)-1)/(sqrt(kappa)+1)) predicts for the remaining reduction (the
+    // bound on the estimated interval overshoots by about half, and every queued step after the
+    // stop still launches its kernels), then short batches
     const double kap = hi / lo, rc = (std::sqrt(kap) - 1.0) / (std::sqrt(kap) + 1.0);
     const double need = std::log(2.0 * hd[k] / (cfg.tol * std::sqrt(out->rho_star) + 1e-300)) / std::log(1.0 / rc);
-    int batch = (int)std::ceil(need) + 1;
+    int batch = need < 1e6 ? (int)std::ceil(need) + 1 : 1000000;
+    if (ctx->last_cheb_steps > 0 && ctx->last_cheb_steps < batch) batch = ctx->last_cheb_steps;
     if (batch < 4) batch = 4;
     const int* done = b.ci + PI_DONE;
     int t = 0;
@@ -602,6 +606,7 @@ int chebyshev_stage(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, PcgBufs
     out->relres = out->rho_star > 0.0 ? hd[0] / std::sqrt(out->rho_star) : 0.0;
     out->cheb_lo = lo;
     out->cheb_hi = hi;
+    ctx->last_cheb_steps = iters - k;
     return IPM_OK;
 }
 
