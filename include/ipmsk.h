@@ -68,7 +68,10 @@ typedef struct ipm_ctx ipm_ctx;
  *   both orders hold the same values. ld is ignored and n must be below 2^31. The index arrays
  *   are trusted: row_ptr / col_ptr must be non-decreasing from 0 to nnz and every index in
  *   range (an index out of range is an out-of-bounds device access, not a returned error).
- *   Duplicate entries are summed; the order within a row or column is free. */
+ *   Duplicate entries are summed; the order within a row or column is free.
+ * Sizes: 1 <= m <= n. A dense A keeps a column strip of all m rows on chip in its passes, so
+ *   m <= 2048 with IPM_F64 or IPM_F32 values and m <= 6400 with IPM_BF16 values; a CSR A allows
+ *   m <= 2^20 and n < 2^31. Larger sizes are IPM_ERR_ARG, reported before any device work. */
 typedef struct {
     int64_t m, n, ld;
     int32_t layout;          /* IPM_DENSE_ROWMAJOR | IPM_CSR */

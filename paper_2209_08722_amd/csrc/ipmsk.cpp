@@ -184,6 +184,9 @@ int check_matrix(ipm_ctx* ctx, const ipm_matrix* A) {
     if (A->ld < A->n) return fail(ctx, IPM_ERR_ARG, "ld < n");
     if ((A->ld * es) % 16 != 0) return fail(ctx, IPM_ERR_ARG, "ld*elem_size must be a multiple of 16 bytes");
     if (reinterpret_cast<uintptr_t>(A->val) % 16 != 0) return fail(ctx, IPM_ERR_ARG, "A->val must be 16-byte aligned");
+    if (strip_plan(A->dtype, (int)A->m, A->n, ctx->num_cu, STRIP_MATVEC).nt <= 0)
+        return fail(ctx, IPM_ERR_ARG, "m=%lld exceeds the dense passes' limit (%d rows with %s values)",
+                    (long long)A->m, A->dtype == IPM_BF16 ? 6400 : 2048, A->dtype == IPM_BF16 ? "BF16" : "FP64/FP32");
     return IPM_OK;
 }
 

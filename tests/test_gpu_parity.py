@@ -287,6 +287,66 @@ def test_argument_errors(ctx):
         assert float(st.x.sum()) == 100.0   # untouched
 
 
+@pytest.mark.parametrize("dtype,mmax", [("f64", 2048), ("f32", 2048), ("bf16", 6400)])
+def test_dense_row_limit(ctx, dtype, mmax):
+    """The largest m a dense A accepts (the strip pass keeps all m rows of a column strip on
+    chip): the matvec at that m, with a ragged n, against the definition; one row more is
+    IPM_ERR_ARG."""
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    rnd = {"f64": lambda a: a, "f32": lpgen.f32_round, "bf16": lpgen.bf16_round}[dtype]
+    n = mmax + 1003
+    A = rnd(rand_lp_matrix(mmax, n, mmax))
+    rng = np.random.default_rng(4)
+    d2 = np.exp(rng.uniform(-3, 3, n))
+    v = rng.standard_normal(mmax)
+    q = host(P.ipm_normal_matvec(ctx, P.Matrix.from_numpy(A, dtype=tdt), dev(d2), dev(v)))
+    ref = A @ (d2 * (A.T @ v))
+    bound = np.abs(A) @ (d2 * (np.abs(A).T @ np.abs(v)))
+    assert np.all(np.abs(q - ref) <= 64 * np.finfo(float).eps * (mmax + np.sqrt(n)) * bound)
+    del A
+    big = P.Matrix.from_numpy(np.ones((mmax + 1, mmax + 8)), dtype=tdt)
+    with pytest.raises(P.IpmError) as ei:
+        P.ipm_normal_matvec(ctx, big, dev(np.ones(mmax + 8)), dev(np.ones(mmax + 1)))
+    assert ei.value.code == -1 and "limit" in str(ei.value)
+
+
+def test_step_rejects_oversized_dense_before_device_work(ctx):
+    m, n = 2049, 2100
+    prob = P.Problem(P.Matrix.from_numpy(np.ones((m, n))), dev(np.ones(m)), dev(np.ones(n)))
+    st = P.State.initial(m, n)
+    with pytest.raises(P.IpmError) as ei:
+        P.ipm_step(ctx, prob, st, P.Params(w=2 * m, s=2))
+    assert ei.value.code == -1
+    assert float(st.x.sum()) == n and float(st.y.abs().sum()) == 0.0   # untouched
+
+
+def test_method_option_errors(ctx):
+    """Out-of-range method switches (feasible, solver, sketch) and a non-zero reserved field
+    are IPM_ERR_ARG, with the state untouched; m > n is rejected."""
+    from dataclasses import replace
+    lp = lpgen.dense_lp(10, 100, seed=1)
+    prob = P.Problem.from_lp(lp)
+    base = P.Params(w=40, s=2)
+
+    class Reserved(P.Params):
+        def c(self):
+            cp = super().c()
+            cp.reserved = 1
+            return cp
+
+    for bad in (replace(base, feasible=2), replace(base, solver=2), replace(base, solver=-1),
+                replace(base, sketch=2), Reserved(w=40, s=2)):
+        st = P.State.initial(10, 100)
+        with pytest.raises(P.IpmError) as ei:
+            P.ipm_step(ctx, prob, st, bad)
+        assert ei.value.code == -1
+        assert float(st.x.sum()) == 100.0
+    tall = P.Matrix.from_numpy(np.ones((12, 8)))
+    with pytest.raises(P.IpmError) as ei:
+        P.ipm_normal_matvec(ctx, tall, dev(np.ones(8)), dev(np.ones(12)))
+    assert ei.value.code == -1
+
+
 def test_config1_full_size_lockstep_and_solve(ctx):
     """The bench workload (500 x 100000, w = 2000, s = 2): two lockstep steps against the
     oracle, then the full GPU solve against the oracle's direct-solver IPM optimum."""
