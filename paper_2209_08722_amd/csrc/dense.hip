@@ -215,79 +215,102 @@ __global__ __launch_bounds__(256, 2) void k_gemm_big(int M, int N, int K, double
             }
 }
 
-// Broadcast lane `lane` of a double held in a VGPR (lane is a compile-time constant here).
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+// Value of lane K of each group of four lanes (DPP quad permutation; K is a constant after the
+// step loop is unrolled).
+template <int K>
+__device__ __forceinline__ double quad_bcast_k(double v) {
+    constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double quad_bcast(double v, int k) {
+    switch (k) {
+        case 0: return quad_bcast_k<0>(v);
+        case 1: return quad_bcast_k<1>(v);
+        case 2: return quad_bcast_k<2>(v);
+        default: return quad_bcast_k<3>(v);
+    }
 }
 
 // Factor the kb x kb diagonal block at (k0, k0) of the partially updated matrix in place
 // (lower triangle) and write its inverse into X's diagonal block (zero above the diagonal).
-// Two waves. The block is loaded with coalesced row reads into LDS and padded to 64 x 64 with the
-// identity (the factor and inverse of diag(A, I) are diag(L, I) and diag(L^-1, I)), so no step
-// below tests bounds. Wave 0, lane t, keeps row t of the matrix in registers: step c of the
-// right-looking factorization takes the pivot from lane c, scales column c, publishes it in LDS
-// (entry c is l_cc) and updates the row with uniform-address (broadcast) reads of that column; for
-// j > t the update only touches the unused upper part. Wave 1, lane t, keeps column t of the
-// inverse and does step c of the column-oriented forward substitution L x = e_t with the same
-// published column and 1/l_cc (x_c = y_c / l_cc, then y_i -= l_ic x_c for i > c), storing X's row c
-// (coalesced). L goes back through LDS for a coalesced write. A pivot that is not positive is
-// recorded in *status (smallest index wins) and replaced by 1 so the remaining work stays finite.
-__global__ __launch_bounds__(128) void k_potrf_diag(double* __restrict__ Lw, int64_t ld, int k0, int kb,
+// The block is padded to 64 x 64 with the identity (the factor and inverse of diag(A, I) are
+// diag(L, I) and diag(L^-1, I)), so no step tests bounds. Eight waves, four threads per row:
+// thread (i, q) of waves 0-3 keeps entries 16q..16q+15 of row i of the matrix in registers, thread
+// (t, q) of waves 4-7 entries 16q..16q+15 of column t of the inverse. Step c of the right-looking
+// factorization reads column c as the owners (quarter c/16) published it before the barrier:
+// entry c is the pivot a_cc, entries below it the updated a_jc, entries above it zero. With
+// g = 1/sqrt(a_cc), the row thread takes its own a_ic from the owner lane of its quad (DPP) and
+// updates a_ij -= (a_ic g^2) a_jc for its 16 columns (the zero entries leave finished columns
+// unchanged; the pivot column itself is then overwritten by l_ic = a_ic g), and the owners of
+// column c+1 publish it for the next step. The inverse threads do the matching step of the
+// column-oriented forward substitution L x = e_t: x_c = y_c g, then y_r -= (x_c g) a_rc. One
+// barrier per step; each thread's 16 reads of the column are independent, so they are all in
+// flight together. A pivot that is not positive is recorded in *status (smallest index wins) and
+// replaced by 1 so the remaining work stays finite.
+__global__ __launch_bounds__(512) void k_potrf_diag(double* __restrict__ Lw, int64_t ld, int k0, int kb,
                                                     double* __restrict__ X, int64_t ldx, int* __restrict__ status) {
-    __shared__ double col[2][64];
-    __shared__ double rinv[64];          // 1 / l_cc
-    __shared__ double Ls[64][65];
-    const int lane = threadIdx.x & 63;
-    const bool fac = threadIdx.x < 64;   // wave 0 factors, wave 1 inverts
-    for (int i = threadIdx.x >> 6; i < 64; i += 2) {
-        double v = (i == lane) ? 1.0 : 0.0;
-        if (i < kb && lane < kb && lane <= i) v = Lw[(int64_t)(k0 + i) * ld + k0 + lane];
-        Ls[i][lane] = v;
-    }
-    __syncthreads();
-    double z[64];   // wave 0: row `lane` of the matrix; wave 1: column `lane` of the inverse
+    __shared__ __align__(16) double colb[2][64];
+    const int tid = threadIdx.x;
+    const bool fac = tid < 256;
+    const int u = tid & 255;
+    const int row = u >> 2;   // row i of the block (factor) or column t of the inverse
+    const int q = u & 3;      // quarter: entries 16q .. 16q+15
+    double z[16];
 #pragma unroll
-    for (int j = 0; j < 64; ++j) z[j] = fac ? Ls[lane][j] : ((j == lane) ? 1.0 : 0.0);
-    double* xcol = X + (int64_t)k0 * ldx + k0 + lane;
-    const bool xw = !fac && lane < kb;
+    for (int k = 0; k < 16; ++k) {
+        const int j = 16 * q + k;
+        double v = (j == row) ? 1.0 : 0.0;
+        if (fac && row < kb && j < kb && j <= row) v = Lw[(int64_t)(k0 + row) * ld + k0 + j];
+        z[k] = v;
+    }
+    if (fac && q == 0) colb[0][row] = z[0];
+    __syncthreads();
     int bad = INT_MAX;
 #pragma unroll
     for (int c = 0; c < 64; ++c) {
-        double* cc = col[c & 1];
+        const double* cb = colb[c & 1];
+        double piv = cb[c];
+        if (!(piv > 0.0)) {
+            bad = min(bad, k0 + c);
+            piv = 1.0;
+        }
+        const double g = rsqrt(piv);
+        double cv[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cv[k] = cb[16 * q + k];
+        const int oq = c >> 4, ok = c & 15;
+        const double own = quad_bcast(z[ok], oq);
         if (fac) {
-            double piv = readlane_d(z[c], c);
-            if (!(piv > 0.0)) {
-                bad = min(bad, k0 + c);
-                piv = 1.0;
-            }
-            // 1/sqrt and sqrt from one reciprocal square root (shorter dependency chain than a
-            // square root followed by a division; the factor only has to be accurate to rounding)
-            const double inv = rsqrt(piv);
-            const double lcc = piv * inv;
-            z[c] = (lane == c) ? lcc : z[c] * inv;
-            cc[lane] = z[c];
-            if (lane == 0) rinv[c] = inv;
-            Ls[lane][c] = z[c];            // L[lane][c], final
+            const double l = (row == c) ? piv * g : own * g;   // l_ic (l_cc on the diagonal)
+            const double sc = l * g;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) z[k] = fma(-sc, cv[k], z[k]);
+            if (q == oq) z[ok] = l;
+            if (c + 1 < 64 && q == ((c + 1) >> 4)) colb[(c + 1) & 1][row] = row > c ? z[(c + 1) & 15] : 0.0;
+        } else {
+            const double x = own * g;   // x_c = y_c / l_cc
+            const double sc = x * g;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) z[k] = fma(-sc, cv[k], z[k]);
+            if (q == oq) z[ok] = x;
         }
         __syncthreads();
+    }
+    if (tid == 0 && bad != INT_MAX) atomicMin(status, bad);
+    if (row >= kb) return;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int j = 16 * q + k;
+        if (j >= kb) continue;
         if (fac) {
-            const double ltc = z[c];
-#pragma unroll
-            for (int j = c + 1; j < 64; ++j) z[j] = fma(-ltc, cc[j], z[j]);
+            if (j <= row) Lw[(int64_t)(k0 + row) * ld + k0 + j] = z[k];
         } else {
-            z[c] = z[c] * rinv[c];         // X[c][lane], final
-            if (xw && c < kb) xcol[(int64_t)c * ldx] = z[c];
-            const double xc = z[c];
-#pragma unroll
-            for (int j = c + 1; j < 64; ++j) z[j] = fma(-cc[j], xc, z[j]);
+            X[(int64_t)(k0 + j) * ldx + k0 + row] = z[k];   // X[j][t], zero above the diagonal
         }
     }
-    if (fac && lane == 0 && bad != INT_MAX) atomicMin(status, bad);
-    __syncthreads();
-    for (int i = threadIdx.x >> 6; i < kb; i += 2)
-        if (lane <= i) Lw[(int64_t)(k0 + i) * ld + k0 + lane] = Ls[i][lane];
 }
 
 __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ X, double* __restrict__ XT, int m) {
@@ -408,7 +431,7 @@ hipError_t launch_sgram_f32(int m, int w, const float* B, double* C, int ksplit,
 hipError_t launch_potrf_diag(double* Lw, int64_t ld, int k0, int kb, double* X, int64_t ldx, int* status,
                              hipStream_t st) {
     if (kb < 1 || kb > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(128), 0, st, Lw, ld, k0, kb, X, ldx, status);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(512), 0, st, Lw, ld, k0, kb, X, ldx, status);
     return hipGetLastError();
 }
 

@@ -228,7 +228,8 @@ def test_solve_warm_prev(ctx, precision):
     assert cold.converged and warm.converged
     oc = float(lp.c @ host(cold.state.x))
     ow = float(lp.c @ host(warm.state.x))
-    assert abs(oc - ow) <= 1e-8 * (1 + abs(oc))
+    # both solves stop at relative gap <= 1e-8: each objective within ~1e-8 of the optimum
+    assert abs(oc - ow) <= 2e-8 * (1 + abs(oc))
     used = sum(i["warm_used"] for i in warm.infos)
     print(f"{precision}: cold CG {sum(i['pcg_iters'] for i in cold.infos)}, "
           f"prev-warm CG {sum(i['pcg_iters'] for i in warm.infos)}, warm kept in {used} steps")

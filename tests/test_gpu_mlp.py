@@ -193,7 +193,8 @@ def test_learned_warm_start_gain(ctx):
         prev = P.solve(ctx, prob, P.Params(w=w, s=2, seed=0, warm_start=P.IPM_WARM_PREV))
         assert cold.converged and lrn.converged and prev.converged
         oc, ol = float(lp.c @ host(cold.state.x)), float(lp.c @ host(lrn.state.x))
-        assert abs(oc - ol) <= 1e-8 * (1 + abs(oc))
+        # both solves stop at relative gap <= 1e-8: each objective within ~1e-8 of the optimum
+        assert abs(oc - ol) <= 2e-8 * (1 + abs(oc))
         cold_it += sum(i["pcg_iters"] for i in cold.infos)
         learn_it += sum(i["pcg_iters"] for i in lrn.infos)
         prev_it += sum(i["pcg_iters"] for i in prev.infos)

@@ -320,4 +320,5 @@ def test_config4s_full_size_solves(ctx, lp4s):
     lo, hi = float(lp.b @ lp.y0), float(lp.c @ lp.x0)
     for obj in (op, om):
         assert lo - 1e-8 * abs(lo) <= obj <= hi + 1e-8 * abs(hi)
-    assert abs(op - om) <= 1e-8 * (1 + abs(op))
+    # both solves stop at relative gap <= 1e-8: each objective within ~1e-8 of the optimum
+    assert abs(op - om) <= 2e-8 * (1 + abs(op))
