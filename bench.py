@@ -15,6 +15,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -299,6 +300,53 @@ def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
     return out
 
 
+def kernel_only(args) -> int:
+    """One kernel family on a seeded random input, for rocprofv3 runs: the factorization of a
+    random FP64 sketch B (m x w), or the matvec over a random A (m x n, N(0,1) in the storage
+    type). Prints the time per call and the rate against the algorithmic work."""
+    import torch
+    import paper_2209_08722_amd as P
+    ctx = P.Context(0)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(0)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if args.gram:
+        m, w = (int(t) for t in args.gram.lower().split("x"))
+        B = torch.randn((m, w), dtype=torch.float64, device="cuda:0", generator=g) / math.sqrt(w)
+        for rep in range(3):
+            ev0.record()
+            P.ipm_precond_factor(ctx, B, want_L=False)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            log(f"factor {m} x {w}: {ms:.3f} ms (Gram {m * m * w / 1e12:.3f} TFLOP SYRK count, "
+                f"{m * m * w / (ms * 1e-3) / 1e12:.1f} TFLOP/s over the whole factorization)")
+    else:
+        shape, dt = args.matvec.lower().split(":")
+        m, n = (int(t) for t in shape.split("x"))
+        tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dt]
+        esz = torch.empty((), dtype=tdt).element_size()
+        ld = (n + 128 // esz - 1) // (128 // esz) * (128 // esz)
+        A = torch.empty((m, ld), dtype=tdt, device="cuda:0")
+        for r0 in range(0, m, 256):
+            r1 = min(m, r0 + 256)
+            A[r0:r1] = torch.randn((r1 - r0, ld), dtype=torch.float32, device="cuda:0", generator=g).to(tdt)
+        mat = P.Matrix(A, n)
+        d2 = torch.exp(torch.empty(n, dtype=torch.float64, device="cuda:0").uniform_(-3, 3, generator=g))
+        v = torch.randn(m, dtype=torch.float64, device="cuda:0", generator=g)
+        nbytes = m * n * esz + 8 * n
+        for rep in range(5):
+            ev0.record()
+            P.ipm_normal_matvec(ctx, mat, d2, v)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            log(f"matvec {m} x {n} {dt}: {ms:.3f} ms ({nbytes / (ms * 1e-3) / 1e9:.0f} GB/s of "
+                f"{nbytes / 1e9:.2f} GB algorithmic bytes)")
+    ctx.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +365,12 @@ def main() -> int:
     ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
+    ap.add_argument("--gram", default="", metavar="MxW",
+                    help="only run the preconditioner factorization (Gram B B^T, Cholesky, L^-1) of a "
+                         "random FP64 m x w sketch, three times (kernel profiling)")
+    ap.add_argument("--matvec", default="", metavar="MxN:DTYPE",
+                    help="only run the normal-equations matvec A D^2 A^T v on a random m x n matrix "
+                         "stored as f64, f32 or bf16, five times (kernel profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -333,6 +387,8 @@ def main() -> int:
         torch.cuda.synchronize()
         log(f"copied {nel * 8} bytes")
         return 0
+    if args.gram or args.matvec:
+        return kernel_only(args)
     import lpgen
     import paper_2209_08722_amd as P
 
