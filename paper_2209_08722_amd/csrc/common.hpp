@@ -66,6 +66,46 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Sum over each group of eight consecutive lanes, left in every lane of the group; all 64 lanes
+// must be active. Three DPP moves: quad permutations [1,0,3,2] and [2,3,0,1] (partners lane^1,
+// lane^2), then the half-row mirror (lane i of eight reads lane 7-i, which holds the other quad's
+// sum). No LDS traffic, unlike a shuffle, and the same pairings as the xor-1/2/4 butterfly.
+constexpr int kDppQuadXor1 = 0xB1;
+constexpr int kDppQuadXor2 = 0x4E;
+constexpr int kDppHalfMirror = 0x141;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <typename V>
+__device__ __forceinline__ V sum8_lanes(V v) {
+    v += dpp_mov<kDppQuadXor1>(v);
+    v += dpp_mov<kDppQuadXor2>(v);
+    v += dpp_mov<kDppHalfMirror>(v);
+    return v;
+}
+
+// Sum over each group of W consecutive lanes (W = 1, 2, 4, 8, 16, 32 or 64).
+template <int W, typename V>
+__device__ __forceinline__ V group_sum(V v) {
+    if constexpr (W == 8) {
+        return sum8_lanes(v);
+    } else {
+#pragma unroll
+        for (int o = 1; o < W; o <<= 1) v += __shfl_xor(v, o, 64);
+        return v;
+    }
+}
+
 __device__ __forceinline__ double wave_min(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
