@@ -268,7 +268,9 @@ int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const dou
  *   (x_i s_i >= (1-gamma) mu and ||r||/||r0|| <= mu/mu0 with r(alpha) = (1-alpha) r), times
  *   theta if below 1; alpha = argmin of mu(alpha) on [0, alpha_max]; x, y, s updated in place
  *   and k incremented only when the step succeeds. If CG fails (stagnation, maxit) or Q is not
- *   SPD, W is redrawn up to max_redraws times with w doubled and s at least 2.
+ *   SPD, W is redrawn up to max_redraws times with w doubled and s at least 2; a redrawn W
+ *   whose Q still factors only with a shift (max_shifts) is kept whatever CG did, since the
+ *   shift then means that kappa(A D) itself, not the draw, puts kappa(Q) beyond 1/u.
  * Synchronizes. */
 int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* params,
              ipm_step_info* info);

@@ -502,7 +502,12 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
         dy = sla.cho_solve((L, True), p)
     else:
         # Redraws: the accepted draw is the last one tried; a draw whose Q is not SPD is
-        # skipped unless it is the last allowed one (then the step fails).
+        # skipped unless it is the last allowed one (then the step fails). A redrawn W (w
+        # doubled, s >= 2) whose Q still factors only with a shift is kept whatever CG did: the
+        # shift means kappa(Q) = kappa(ADW)^2 is beyond 1/u, and once the draw is a good
+        # embedding kappa(ADW) tracks kappa(AD), which further draws do not change. A first draw
+        # that needs a shift is redrawn: with s = 1 or a narrow W the draw itself can leave B
+        # nearly rank deficient.
         res = None
         for attempt in range(prm.max_redraws + 1):
             w, sk = sketch_size(prm.w, prm.s, attempt)
@@ -525,7 +530,7 @@ def step(A, b, c, st: State, prm: Params, mode: str = "sketch", dy0=None,
             else:
                 res = pcg(matvec, L, p, prm.tol_pcg, prm.maxit_pcg, dy0=dy0,
                           stag_window=prm.stag_window, stag_ratio=prm.stag_ratio)
-            if res.status in (OK, ERR_BREAKDOWN):
+            if res.status in (OK, ERR_BREAKDOWN) or (shift > 0.0 and attempt > 0):
                 break
         info.extra.update(attempts=attempt + 1, w_used=w, s_used=sk, shift=shift)
         info.pcg_iters, info.pcg_status, info.pcg_relres = res.iters, res.status, res.relres

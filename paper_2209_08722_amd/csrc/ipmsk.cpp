@@ -1168,7 +1168,10 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
             info->status = IPM_ERR_BREAKDOWN;
             return fail(ctx, IPM_ERR_BREAKDOWN, "CG breakdown");
         }
-        if (po.status == IPM_OK) break;
+        // a redrawn W whose Q still factors only with a shift is kept: kappa(Q) beyond 1/u then
+        // comes from kappa(AD), which further draws do not change (a first draw that needs a
+        // shift is redrawn, since a narrow or s = 1 draw can itself leave B nearly rank deficient)
+        if (po.status == IPM_OK || (shift > 0.0 && a > 0)) break;
     }
     info->attempts = attempts;
     info->w_used = w_used;
