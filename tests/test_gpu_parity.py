@@ -242,6 +242,35 @@ def test_step_lockstep_ragged(ctx):
     _lockstep(ctx, lp, oprm, P.Params(w=92, s=2, seed=7), steps=10, rtol_state=1e-8)
 
 
+@pytest.mark.parametrize("near", [True, False])
+def test_redraw_rule_matches_oracle(ctx, near):
+    """CG capped at 2 iterations fails on every draw. With a well-conditioned A all four draws are
+    tried, as in the oracle's step. With nearly dependent rows (kappa(Q) ~ 1e20) whether a draw's
+    Cholesky needs a shift is decided by rounding noise in the pivot, so the GPU and the oracle may
+    stop at different draws; the GPU must stop before the last draw only on a redraw that needed
+    a shift."""
+    rng = np.random.default_rng(5)
+    m, n = 6, 600
+    A = rng.standard_normal((m, n))
+    if near:
+        A[1] = A[0] + 1e-10 * rng.standard_normal(n)
+    x0 = rng.uniform(0.5, 1.5, n)
+    y0, s0 = rng.standard_normal(m), rng.uniform(0.5, 1.5, n)
+    b, c = A @ x0, A.T @ y0 + s0
+    st = oipm.initial_state(A, b, c)
+    st, _ = oipm.step(A, b, c, st, oipm.Params(w=24, s=2, seed=1), "sketch")
+    _, oinfo = oipm.step(A, b, c, st, oipm.Params(w=24, s=2, seed=1, maxit_pcg=2), "sketch")
+    prob = P.Problem(P.Matrix.from_numpy(A), dev(b), dev(c))
+    ginfo = P.ipm_step(ctx, prob, _gpu_state(st), P.Params(w=24, s=2, seed=1, maxit_pcg=2))
+    assert ginfo["pcg_status"] == oinfo.pcg_status == oipm.PCG_MAXIT
+    assert ginfo["w_used"] == 24 << (ginfo["attempts"] - 1)
+    if near:
+        assert ginfo["attempts"] == 4 or (ginfo["attempts"] >= 2 and ginfo["shift"] > 0)
+    else:
+        assert ginfo["attempts"] == oinfo.extra["attempts"] == 4
+        assert ginfo["shift"] == oinfo.extra["shift"] == 0
+
+
 def test_solve_config0_matches_oracle(ctx):
     lp = lpgen.config(0)
     res = P.solve(ctx, P.Problem.from_lp(lp), P.Params(w=200, s=1, seed=0))

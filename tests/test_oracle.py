@@ -578,3 +578,33 @@ def test_planted_transposed_sketch_is_caught():
         for r in range(3):
             Bb[:, bucket[j, (r + 1) % 3]] += A[:, j] * d[j] * sign[j, r] / np.sqrt(3)
     assert not np.allclose(sketch.sketch_ADW(A, d, 12, 3, 11, 4), Bb)
+
+
+def _near_dependent_lp(near: bool):
+    """6 x 600 LP from the generic rule; with ``near`` its second row is the first plus 1e-10 noise,
+    so kappa(A D) ~ 1e10 and every draw's Q = B B^T is beyond 1/u."""
+    rng = np.random.default_rng(5)
+    m, n = 6, 600
+    A = rng.standard_normal((m, n))
+    if near:
+        A[1] = A[0] + 1e-10 * rng.standard_normal(n)
+    x0 = rng.uniform(0.5, 1.5, n)
+    y0, s0 = rng.standard_normal(m), rng.uniform(0.5, 1.5, n)
+    return A, A @ x0, A.T @ y0 + s0
+
+
+@pytest.mark.parametrize("near", [True, False])
+def test_redraw_rule_keeps_shifted_redraw(near):
+    """Redraws (reading of the failed-solve case): CG capped at 2 iterations fails on every draw.
+    When Q factors only with a shift on every draw (kappa(AD) itself beyond sqrt(1/u)), the first
+    redraw is kept (2 attempts, shift > 0); with a well-conditioned A all max_redraws + 1 draws are
+    tried (4 attempts, no shift)."""
+    A, b, c = _near_dependent_lp(near)
+    st = ipm.initial_state(A, b, c)
+    st, _ = ipm.step(A, b, c, st, ipm.Params(w=24, s=2, seed=1), "sketch")
+    _, info = ipm.step(A, b, c, st, ipm.Params(w=24, s=2, seed=1, maxit_pcg=2), "sketch")
+    assert info.pcg_status == ipm.PCG_MAXIT
+    if near:
+        assert info.extra["attempts"] == 2 and info.extra["w_used"] == 48 and info.extra["shift"] > 0
+    else:
+        assert info.extra["attempts"] == 4 and info.extra["w_used"] == 192 and info.extra["shift"] == 0
