@@ -302,8 +302,9 @@ def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
 
 def kernel_only(args) -> int:
     """One kernel family on a seeded random input, for rocprofv3 runs: the factorization of a
-    random FP64 sketch B (m x w), or the matvec over a random A (m x n, N(0,1) in the storage
-    type). Prints the time per call and the rate against the algorithmic work."""
+    random FP64 sketch B (m x w), the Gaussian sketch of a random FP64 A, or the matvec over a
+    random A (m x n, N(0,1) in the storage type). Prints the time per call and the rate against
+    the algorithmic work."""
     import torch
     import paper_2209_08722_amd as P
     ctx = P.Context(0)
@@ -321,6 +322,21 @@ def kernel_only(args) -> int:
             ms = ev0.elapsed_time(ev1)
             log(f"factor {m} x {w}: {ms:.3f} ms (Gram {m * m * w / 1e12:.3f} TFLOP SYRK count, "
                 f"{m * m * w / (ms * 1e-3) / 1e12:.1f} TFLOP/s over the whole factorization)")
+    elif args.gauss:
+        shape, ws = args.gauss.lower().split(":")
+        m, n = (int(t) for t in shape.split("x"))
+        w = int(ws)
+        A = torch.randn((m, n), dtype=torch.float64, device="cuda:0", generator=g)
+        mat = P.Matrix(A, n) if n % 16 == 0 else P.Matrix.from_numpy(A.cpu().numpy())
+        d = torch.exp(torch.empty(n, dtype=torch.float64, device="cuda:0").uniform_(-3, 3, generator=g))
+        for rep in range(3):
+            ev0.record()
+            P.ipm_sketch_gaussian(ctx, mat, d, 5, rep, w)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            log(f"gaussian sketch {m} x {n}, w = {w}: {ms:.3f} ms ({2.0 * m * n * w / (ms * 1e-3) / 1e12:.1f} "
+                f"TFLOP/s on 2 m n w)")
     else:
         shape, dt = args.matvec.lower().split(":")
         m, n = (int(t) for t in shape.split("x"))
@@ -368,6 +384,9 @@ def main() -> int:
     ap.add_argument("--gram", default="", metavar="MxW",
                     help="only run the preconditioner factorization (Gram B B^T, Cholesky, L^-1) of a "
                          "random FP64 m x w sketch, three times (kernel profiling)")
+    ap.add_argument("--gauss", default="", metavar="MxN:W",
+                    help="only run the Gaussian sketch B = A D W of a random FP64 m x n matrix with w "
+                         "columns of W, three times (kernel profiling)")
     ap.add_argument("--matvec", default="", metavar="MxN:DTYPE",
                     help="only run the normal-equations matvec A D^2 A^T v on a random m x n matrix "
                          "stored as f64, f32 or bf16, five times (kernel profiling)")
@@ -387,7 +406,7 @@ def main() -> int:
         torch.cuda.synchronize()
         log(f"copied {nel * 8} bytes")
         return 0
-    if args.gram or args.matvec:
+    if args.gram or args.matvec or args.gauss:
         return kernel_only(args)
     import lpgen
     import paper_2209_08722_amd as P

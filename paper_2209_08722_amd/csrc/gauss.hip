@@ -11,7 +11,9 @@
 // atomic accumulation into an FP64 B that the caller cleared. Generating W (two SplitMix64
 // outputs, a log, a square root and a cosine in FP64 per entry) costs about as much as the MFMA
 // work it feeds, so the tile is tall: each generated entry is used by 256 rows of A (128-row
-// tiles ran at 21 TFLOP/s on 500 x 100000 x 2000, generation-bound).
+// tiles ran at 21 TFLOP/s on 500 x 100000 x 2000, generation-bound). At 256 rows neither unit is
+// saturated (MFMA about 37 % busy, vector ALUs about 11 % active): the two barriers per K slab
+// around the LDS staging bound the kernel.
 #include "kernels.hpp"
 
 namespace ipmsk {
