@@ -11,9 +11,10 @@
 // atomic accumulation into an FP64 B that the caller cleared. Generating W (two SplitMix64
 // outputs, a log, a square root and a cosine in FP64 per entry) costs about as much as the MFMA
 // work it feeds, so the tile is tall: each generated entry is used by 256 rows of A (128-row
-// tiles ran at 21 TFLOP/s on 500 x 100000 x 2000, generation-bound). At 256 rows neither unit is
-// saturated (MFMA about 37 % busy, vector ALUs about 11 % active): the two barriers per K slab
-// around the LDS staging bound the kernel.
+// tiles ran at 21 TFLOP/s on 500 x 100000 x 2000, generation-bound). The slabs are double-
+// buffered in LDS (one barrier per slab). At 256 rows neither unit is saturated (MFMA about 38 %
+// busy, vector ALUs about 11 % active) and halving the barriers gained only 3 %: the kernel is
+// latency-bound, most likely on the A loads issued one slab ahead.
 #include "kernels.hpp"
 
 namespace ipmsk {
@@ -45,8 +46,8 @@ __global__ __launch_bounds__(GNT, 1) void k_sketch_gauss(int m, int64_t n, int w
     const int tm = blockIdx.y * GBM, tn = blockIdx.x * GBN;
     const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
     const int64_t kend = min(n, kbeg + kchunk);
-    __shared__ double As[GKS][GLDA];
-    __shared__ double Ws[GKS][GLDW];
+    __shared__ double As[2][GKS][GLDA];   // double-buffered slabs: one barrier per slab
+    __shared__ double Ws[2][GKS][GLDW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wr = wid >> 1, wc = wid & 1;
     const int sr = tid >> 1, sh = (tid & 1) * 8;          // A slab: row (of 256), first of 8 columns
@@ -73,11 +74,11 @@ __global__ __launch_bounds__(GNT, 1) void k_sketch_gauss(int m, int64_t n, int w
             pw[q] = (j < kend && c < w) ? gauss_entry(key, (uint64_t)j * (uint64_t)w + (uint64_t)c, inv_sqrt_w) : 0.0;
         }
     };
-    auto commit = [&]() {
+    auto commit = [&](int bb) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) As[sh + q][sr] = pa[q];
+        for (int q = 0; q < 8; ++q) As[bb][sh + q][sr] = pa[q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Ws[wk][wn + q] = pw[q];
+        for (int q = 0; q < 4; ++q) Ws[bb][wk][wn + q] = pw[q];
     };
 
     d4_t acc[4][4];
@@ -86,26 +87,33 @@ __global__ __launch_bounds__(GNT, 1) void k_sketch_gauss(int m, int64_t n, int w
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = d4_t{0.0, 0.0, 0.0, 0.0};
 
-    if (kbeg < kend) stage(kbeg);
+    if (kbeg < kend) {
+        stage(kbeg);
+        commit(0);
+    }
+    __syncthreads();
+    int cur = 0;
     for (int64_t k0 = kbeg; k0 < kend; k0 += GKS) {
-        __syncthreads();
-        commit();
-        __syncthreads();
-        if (k0 + GKS < kend) stage(k0 + GKS);   // next slab (loads and generation) during the MFMAs
+        const bool more = k0 + GKS < kend;
+        if (more) stage(k0 + GKS);   // next slab (loads and generation) during the MFMAs
 #pragma unroll
         for (int ks = 0; ks < GKS / 4; ++ks) {
             const int kq = ks * 4 + (lane >> 4);
             double a[4], b[4];
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi) a[bi] = As[kq][wr * 64 + bi * 16 + (lane & 15)];
+            for (int bi = 0; bi < 4; ++bi) a[bi] = As[cur][kq][wr * 64 + bi * 16 + (lane & 15)];
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) b[bj] = Ws[kq][wc * 64 + bj * 16 + (lane & 15)];
+            for (int bj = 0; bj < 4; ++bj) b[bj] = Ws[cur][kq][wc * 64 + bj * 16 + (lane & 15)];
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj)
                     acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
         }
+        // the other buffer was last read in the previous slab, before the barrier that ended it
+        if (more) commit(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
     }
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
