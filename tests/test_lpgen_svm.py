@@ -2,6 +2,8 @@
 checked against what the formulation fixes: the LP optimum found by HiGHS is a separating w
 with margin 1 whose l1 norm is the optimal value, and the oracle's IPM with and without the
 v-correction reaches that optimum."""
+import os
+
 import numpy as np
 import pytest
 from scipy.optimize import linprog
@@ -31,3 +33,11 @@ def test_oracle_solves_svm_lp(vcorr):
     res = oipm.solve(lp.A, lp.b, lp.c, oipm.Params(w=80, s=2, seed=0, vcorr=vcorr), "sketch")
     assert res.converged
     assert abs(float(lp.c @ res.state.x) - ref.fun) <= 1e-7 * (1 + abs(ref.fun))
+
+
+def test_svm_shapes_are_table1():
+    """The four l1-SVM shapes and sketch widths are those Table 1 prints (tests/golden)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table1_svm_shapes.txt")
+    with open(path) as f:
+        rows = [line.split() for line in f if line.strip() and not line.startswith("#")]
+    assert {r[0]: dict(m=int(r[1]), N=int(r[2]), w=int(r[3])) for r in rows} == lpgen.SVM_SHAPES
