@@ -128,6 +128,28 @@ def test_precond_factor(ctx, m, w):
     assert np.linalg.norm(Linv @ Lref - np.eye(m)) <= 1e-13 * kap * kap * np.sqrt(m)
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gpu_preconditioned_spectrum_lemma_cond3(ctx, seed):
+    """The spectral condition the method relies on (eq. pdcond1, Lemma cond3), on the GPU's own
+    sketch and factor: with a wide embedding (w = 100 m, s = 8) the eigenvalues of
+    X A D^2 A^T X^T (X = L^{-1} from ipm_precond_factor of B = ipm_sketch) lie in
+    [2/(2+zeta), 2/(2-zeta)], zeta = 1/2, and equal the oracle's for the same W."""
+    lp = lpgen.tiny_lp(20, 2000, 8)
+    rng = np.random.default_rng(2)
+    d2 = np.exp(rng.uniform(-4, 4, lp.n))
+    B = P.ipm_sketch(ctx, P.Matrix.from_numpy(lp.A), dev(np.sqrt(d2)), seed, 0, 2000, 8)
+    _, Linv = P.ipm_precond_factor(ctx, B)
+    X = host(Linv)
+    M = (lp.A * d2) @ lp.A.T
+    ev = np.linalg.eigvalsh(X @ M @ X.T)
+    zeta = 0.5
+    assert ev.min() >= 2 / (2 + zeta) and ev.max() <= 2 / (2 - zeta)
+    Bo = osk.sketch_ADW(lp.A, np.sqrt(d2), 2000, 8, seed, 0)
+    Lo = np.linalg.cholesky(Bo @ Bo.T)
+    evo = np.linalg.eigvalsh(sla.solve_triangular(Lo, sla.solve_triangular(Lo, M, lower=True).T, lower=True))
+    assert np.allclose(ev, evo, rtol=1e-9, atol=0)
+
+
 def test_precond_factor_reports_bad_pivot(ctx):
     rng = np.random.default_rng(0)
     B = rng.standard_normal((80, 160))
