@@ -126,8 +126,26 @@ template <bool TRANS_B, bool LOWER, typename TIN>
 __global__ __launch_bounds__(256, 2) void k_gemm_big(int M, int N, int K, double alpha, const TIN* __restrict__ A,
                                                   int64_t lda, const TIN* __restrict__ B, int64_t ldb, double beta,
                                                   double* C, int64_t ldc, int kchunk, int atomic) {
-    const int tm = blockIdx.y * BT, tn = blockIdx.x * BT;
-    if (LOWER && tn >= tm + BT) return;
+    // Tile of this block. The grid is one-dimensional over the tiles (lower tiles only when
+    // LOWER), blockIdx.z the split-K slice. Consecutive workgroups go to the chip's 8 XCDs in
+    // turn, so workgroup L is given tile (L mod 8) * (T / 8) + L / 8 (remainder spread over the
+    // first XCDs): each XCD works through a contiguous band of the row-major tile order, and
+    // tiles that read the same row panels of A and B share that XCD's L2.
+    const int ntx = (N + BT - 1) / BT;
+    const unsigned T = gridDim.x, L = blockIdx.x;
+    const unsigned xcd = L % 8u, per = T / 8u, rem = T % 8u;
+    const unsigned l = xcd * per + (xcd < rem ? xcd : rem) + L / 8u;
+    int ty, tx;
+    if (LOWER) {
+        ty = (int)((sqrt(8.0 * (double)l + 1.0) - 1.0) * 0.5);
+        while ((unsigned)((ty + 1) * (ty + 2) / 2) <= l) ++ty;
+        while ((unsigned)(ty * (ty + 1) / 2) > l) --ty;
+        tx = (int)l - ty * (ty + 1) / 2;
+    } else {
+        ty = (int)l / ntx;
+        tx = (int)l - ty * ntx;
+    }
+    const int tm = ty * BT, tn = tx * BT;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
     __shared__ double As[BK][BLD];
@@ -382,7 +400,11 @@ hipError_t gemm_big_go(int M, int N, int K, double alpha, const TIN* A, int64_t 
     kchunk = ((kchunk + BK - 1) / BK) * BK;
     if (kchunk < BK) kchunk = BK;
     ksplit = K > 0 ? (K + kchunk - 1) / kchunk : 1;
-    const dim3 grid((N + BT - 1) / BT, (M + BT - 1) / BT, ksplit);
+    // LOWER products are square (Gram, trailing updates): the grid covers the lower tiles only
+    if (LO && M != N) return hipErrorInvalidValue;
+    const int nt = (M + BT - 1) / BT, ntx = (N + BT - 1) / BT;
+    const unsigned tiles = LO ? (unsigned)(nt * (nt + 1) / 2) : (unsigned)(nt * ntx);
+    const dim3 grid(tiles, 1, ksplit);
     IPM_LAUNCH((k_gemm_big<TB, LO, TIN>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
                kchunk, ksplit > 1 ? 1 : 0);
     return hipGetLastError();
