@@ -300,11 +300,23 @@ def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
     return out
 
 
+def random_rows(torch, g, m: int, n: int, tdt):
+    """An m x n N(0,1) matrix in the storage type, rows padded to 128 bytes, drawn 256 rows at a
+    time in FP32 (bounded temporary memory)."""
+    esz = torch.empty((), dtype=tdt).element_size()
+    ld = (n + 128 // esz - 1) // (128 // esz) * (128 // esz)
+    A = torch.empty((m, ld), dtype=tdt, device="cuda:0")
+    for r0 in range(0, m, 256):
+        r1 = min(m, r0 + 256)
+        A[r0:r1] = torch.randn((r1 - r0, ld), dtype=torch.float32, device="cuda:0", generator=g).to(tdt)
+    return A
+
+
 def kernel_only(args) -> int:
     """One kernel family on a seeded random input, for rocprofv3 runs: the factorization of a
-    random FP64 sketch B (m x w), the Gaussian sketch of a random FP64 A, or the matvec over a
-    random A (m x n, N(0,1) in the storage type). Prints the time per call and the rate against
-    the algorithmic work."""
+    random FP64 sketch B (m x w), the Gaussian sketch of a random FP64 A, the sparse-embedding
+    sketch (s = 2) or the matvec over a random A (m x n, N(0,1) in the storage type). Prints the
+    time per call and the rate against the algorithmic work."""
     import torch
     import paper_2209_08722_amd as P
     ctx = P.Context(0)
@@ -337,17 +349,29 @@ def kernel_only(args) -> int:
             ms = ev0.elapsed_time(ev1)
             log(f"gaussian sketch {m} x {n}, w = {w}: {ms:.3f} ms ({2.0 * m * n * w / (ms * 1e-3) / 1e12:.1f} "
                 f"TFLOP/s on 2 m n w)")
+    elif args.sketch:
+        shape, ws, dt = args.sketch.lower().split(":")
+        m, n = (int(t) for t in shape.split("x"))
+        w = int(ws)
+        tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dt]
+        esz = torch.empty((), dtype=tdt).element_size()
+        mat = P.Matrix(random_rows(torch, g, m, n, tdt), n)
+        d = torch.exp(torch.empty(n, dtype=torch.float64, device="cuda:0").uniform_(-3, 3, generator=g))
+        nbytes = m * n * esz + 8 * n + m * w * 8
+        for rep in range(5):
+            ev0.record()
+            P.ipm_sketch(ctx, mat, d, 5, rep, w, 2)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            log(f"sparse sketch {m} x {n} {dt}, w = {w}, s = 2: {ms:.3f} ms ({nbytes / (ms * 1e-3) / 1e9:.0f} "
+                f"GB/s of {nbytes / 1e9:.3f} GB algorithmic bytes: A, d and B once)")
     else:
         shape, dt = args.matvec.lower().split(":")
         m, n = (int(t) for t in shape.split("x"))
         tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dt]
         esz = torch.empty((), dtype=tdt).element_size()
-        ld = (n + 128 // esz - 1) // (128 // esz) * (128 // esz)
-        A = torch.empty((m, ld), dtype=tdt, device="cuda:0")
-        for r0 in range(0, m, 256):
-            r1 = min(m, r0 + 256)
-            A[r0:r1] = torch.randn((r1 - r0, ld), dtype=torch.float32, device="cuda:0", generator=g).to(tdt)
-        mat = P.Matrix(A, n)
+        mat = P.Matrix(random_rows(torch, g, m, n, tdt), n)
         d2 = torch.exp(torch.empty(n, dtype=torch.float64, device="cuda:0").uniform_(-3, 3, generator=g))
         v = torch.randn(m, dtype=torch.float64, device="cuda:0", generator=g)
         nbytes = m * n * esz + 8 * n
@@ -387,6 +411,9 @@ def main() -> int:
     ap.add_argument("--gauss", default="", metavar="MxN:W",
                     help="only run the Gaussian sketch B = A D W of a random FP64 m x n matrix with w "
                          "columns of W, three times (kernel profiling)")
+    ap.add_argument("--sketch", default="", metavar="MxN:W:DTYPE",
+                    help="only run the sparse-embedding sketch (s = 2) of a random m x n matrix stored "
+                         "as f64, f32 or bf16 with w buckets, five times (kernel profiling)")
     ap.add_argument("--matvec", default="", metavar="MxN:DTYPE",
                     help="only run the normal-equations matvec A D^2 A^T v on a random m x n matrix "
                          "stored as f64, f32 or bf16, five times (kernel profiling)")
@@ -406,7 +433,7 @@ def main() -> int:
         torch.cuda.synchronize()
         log(f"copied {nel * 8} bytes")
         return 0
-    if args.gram or args.matvec or args.gauss:
+    if args.gram or args.matvec or args.gauss or args.sketch:
         return kernel_only(args)
     import lpgen
     import paper_2209_08722_amd as P

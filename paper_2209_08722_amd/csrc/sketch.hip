@@ -19,8 +19,14 @@ constexpr int SNT = 1024;     // 16 waves per block: the LDS bucket array limits
                               // the block itself must carry enough waves to hide load latency
 constexpr int SUNROLL = 4;    // columns per thread per pass (independent loads in flight)
 
+// Columns per thread per pass of the bucket kernel: R rows x U columns of A in flight per thread,
+// at most 8 values, so the kernel stays within 64 VGPRs (eight waves per SIMD: two 16-wave blocks
+// per CU whenever two bucket arrays fit in LDS).
+template <int R>
+constexpr int sketch_unroll() { return R >= 8 ? 1 : (R >= 4 ? 2 : 4); }
+
 template <typename T, typename BT, int R>
-__global__ __launch_bounds__(SNT) void k_sketch_lds(const T* __restrict__ A, int m, int64_t n, int64_t ld,
+__global__ __launch_bounds__(SNT) __attribute__((amdgpu_waves_per_eu(8))) void k_sketch_lds(const T* __restrict__ A, int m, int64_t n, int64_t ld,
                                                     const double* __restrict__ dv, int d_is_d2, HashKeys hk, int w,
                                                     int64_t cpc, BT* __restrict__ B, int atomic) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -32,11 +38,12 @@ __global__ __launch_bounds__(SNT) void k_sketch_lds(const T* __restrict__ A, int
     for (int i = tid; i < R * w; i += SNT) bk[i] = 0.0;
     __syncthreads();
     const int s = hk.s;
-    for (int64_t jj = jb + tid; jj < je; jj += (int64_t)SNT * SUNROLL) {
-        double av[SUNROLL][R];
-        double dj[SUNROLL];
+    constexpr int U = sketch_unroll<R>();
+    for (int64_t jj = jb + tid; jj < je; jj += (int64_t)SNT * U) {
+        double av[U][R];
+        double dj[U];
 #pragma unroll
-        for (int u = 0; u < SUNROLL; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int64_t j = jj + (int64_t)u * SNT;
             const bool ok = j < je;
             double dd = ok ? dv[ok ? j : 0] : 0.0;
@@ -48,7 +55,7 @@ __global__ __launch_bounds__(SNT) void k_sketch_lds(const T* __restrict__ A, int
             }
         }
 #pragma unroll
-        for (int u = 0; u < SUNROLL; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int64_t j = jj + (int64_t)u * SNT;
             if (j >= je) continue;
             for (int r = 0; r < s; ++r) {
@@ -222,16 +229,26 @@ SketchPlan sketch_plan(int m, int64_t n, int w, int out_f64, int num_cu) {
         return sp;
     }
     sp.rows_per_block = R;
+    sp.lds = (size_t)R * w * esz;
+    // Blocks resident at once: two per CU when two bucket arrays fit in LDS (the kernel is held to
+    // eight waves per SIMD), else one. With the column range split into c chunks the grid runs in
+    // ceil(row_blocks c / slots) rounds; per row a block streams n / c columns and clears, then
+    // adds back, its w buckets (weighted as 2 w columns), and c minimises rounds x that sum (the
+    // fewest chunks among equals).
     const int row_blocks = (m + R - 1) / R;
-    const int target = 2 * num_cu;
-    int chunks = (target + row_blocks - 1) / row_blocks;
-    const int64_t max_chunks = (n + 4095) / 4096;   // keep at least 4096 columns per block
-    if (chunks > max_chunks) chunks = (int)max_chunks;
-    if (chunks < 1) chunks = 1;
+    const int slots = num_cu * (2 * sp.lds <= budget_max ? 2 : 1);
+    const int64_t by_cols = (n + 4095) / 4096;   // keep at least 4096 columns per block
+    const int64_t max_chunks = by_cols < 64 ? by_cols : 64;
+    int chunks = 1;
+    double best = 0.0;
+    for (int c = 1; c <= max_chunks; ++c) {
+        const double rounds = (double)(((int64_t)row_blocks * c + slots - 1) / slots);
+        const double cost = rounds * ((double)n / c + 2.0 * w);
+        if (c == 1 || cost < best - 1e-12) { best = cost; chunks = c; }
+    }
     sp.chunks = chunks;
     sp.cols_per_chunk = (n + chunks - 1) / chunks;
     sp.atomic = chunks > 1;
-    sp.lds = (size_t)R * w * esz;
     return sp;
 }
 
