@@ -300,6 +300,31 @@ def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
     return out
 
 
+def stream_probe(P, ctx, nbytes: int, reps: int = 20) -> dict:
+    """Attainable HBM bandwidth on this GPU for the streaming passes' access pattern: the read
+    pass of ipm_stream_read and the copy pass of ipm_stream_copy over nbytes (HIP events at each
+    pass's own start and end, every launch; the first launch of each is a warm-up)."""
+    import torch
+    count = nbytes // 8
+    x = torch.full((count,), 0.5, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    out = {"bytes": count * 8}
+    for name, kid, call, moved in (
+            ("read", P.native.IPM_KERNEL_STREAM_READ, lambda: P.ipm_stream_read(ctx, x), count * 8),
+            ("copy", P.native.IPM_KERNEL_STREAM_COPY, lambda: P.ipm_stream_copy(ctx, x, y), 2 * count * 8)):
+        call()
+        torch.cuda.synchronize()
+        ctx.set_timing(1)
+        for _ in range(reps):
+            call()
+        ms, cnt = ctx.kernel_time(kid)
+        ctx.set_timing(False)
+        out[f"{name}_gbps"] = moved / (ms / cnt * 1e-3) / 1e9
+        out[f"{name}_us"] = ms / cnt * 1e3
+    del x, y
+    return out
+
+
 def random_rows(torch, g, m: int, n: int, tdt):
     """An m x n N(0,1) matrix in the storage type, rows padded to 128 bytes, drawn 256 rows at a
     time in FP32 (bounded temporary memory)."""
@@ -315,8 +340,8 @@ def random_rows(torch, g, m: int, n: int, tdt):
 def kernel_only(args) -> int:
     """One kernel family on a seeded random input, for rocprofv3 runs: the factorization of a
     random FP64 sketch B (m x w), the Gaussian sketch of a random FP64 A, the sparse-embedding
-    sketch (s = 2) or the matvec over a random A (m x n, N(0,1) in the storage type). Prints the
-    time per call and the rate against the algorithmic work."""
+    sketch (s = 2), the matvec over a random A (m x n, N(0,1) in the storage type) or the
+    bandwidth probes. Prints the time per call and the rate against the algorithmic work."""
     import torch
     import paper_2209_08722_amd as P
     ctx = P.Context(0)
@@ -349,6 +374,10 @@ def kernel_only(args) -> int:
             ms = ev0.elapsed_time(ev1)
             log(f"gaussian sketch {m} x {n}, w = {w}: {ms:.3f} ms ({2.0 * m * n * w / (ms * 1e-3) / 1e12:.1f} "
                 f"TFLOP/s on 2 m n w)")
+    elif args.stream:
+        r = stream_probe(P, ctx, args.stream)
+        log(f"stream probe {r['bytes'] / 1e9:.3f} GB: read {r['read_us']:.1f} us = {r['read_gbps']:.0f} GB/s; "
+            f"copy {r['copy_us']:.1f} us = {r['copy_gbps']:.0f} GB/s (read + written bytes)")
     elif args.sketch:
         shape, ws, dt = args.sketch.lower().split(":")
         m, n = (int(t) for t in shape.split("x"))
@@ -411,6 +440,9 @@ def main() -> int:
     ap.add_argument("--gauss", default="", metavar="MxN:W",
                     help="only run the Gaussian sketch B = A D W of a random FP64 m x n matrix with w "
                          "columns of W, three times (kernel profiling)")
+    ap.add_argument("--stream", type=int, default=0, metavar="BYTES",
+                    help="only run the bandwidth probes (ipm_stream_read, ipm_stream_copy) over BYTES "
+                         "bytes, 21 times each (kernel profiling)")
     ap.add_argument("--sketch", default="", metavar="MxN:W:DTYPE",
                     help="only run the sparse-embedding sketch (s = 2) of a random m x n matrix stored "
                          "as f64, f32 or bf16 with w buckets, five times (kernel profiling)")
@@ -433,7 +465,7 @@ def main() -> int:
         torch.cuda.synchronize()
         log(f"copied {nel * 8} bytes")
         return 0
-    if args.gram or args.matvec or args.gauss or args.sketch:
+    if args.gram or args.matvec or args.gauss or args.sketch or args.stream:
         return kernel_only(args)
     import lpgen
     import paper_2209_08722_amd as P
@@ -500,6 +532,8 @@ def main() -> int:
     esz = 8
     a_bytes = m * n * esz
     mv_bytes = a_bytes + n * 8                     # A once + d^2 (algorithmic, per launch)
+    log("stream probe at the matvec's bytes")
+    probe = stream_probe(P, ctx, mv_bytes)
     sk_bytes = a_bytes + n * 8 + m * w * 8         # A once + d + B written
     gram_flops = float(m) * m * w                  # SYRK count m^2 w
     mv_avg = mv_ms / max(mv_n, 1) * 1e-3
@@ -530,7 +564,12 @@ def main() -> int:
                      "frac": (mv_gbs / HBM_PEAK_GBS) if mv_gbs else None, "traffic": traffic,
                      "kernel": "CG matvec pass q = A D^2 A^T v (k_strip OpMatvec)",
                      "algorithmic_bytes_per_launch": mv_bytes, "avg_launch_us": mv_avg * 1e6,
-                     "timed_launches": mv_n, "timing_period": TIMING_PERIOD},
+                     "timed_launches": mv_n, "timing_period": TIMING_PERIOD,
+                     "measured_peak": probe["read_gbps"],
+                     "frac_measured": (mv_gbs / probe["read_gbps"]) if mv_gbs else None,
+                     "measured_peak_kernel": "ipm_stream_read: read-only pass over the same bytes, same access "
+                                             "pattern (k_stream_read)"},
+        "stream_probe": probe,
         "matvec_hbm_gbps": mv_gbs,
         "sketch_hbm_gbps": sk_gbs,
         "gram_tflops": gr_tf,

@@ -349,12 +349,30 @@ int ipm_mlp_predict(ipm_ctx* ctx, const ipm_mlp* net, int64_t n, const double* d
 int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v,
                       double* q);
 
+/* Attainable-bandwidth probes: the measured denominators, beside the vendor's 8 TB/s, for the
+ * streaming passes over A (the matvec, the sketch, the residual and direction passes). Not
+ * steps of the method; both run on the context's stream and use its access pattern (contiguous
+ * per-block ranges of non-temporal 16-byte loads).
+ *
+ * ipm_stream_read: out[0] = the sum of the `count` FP64 words at x, accumulated in FP64 (per
+ * block, then over the blocks in a fixed order, so the result is reproducible). x [device],
+ * 16-byte aligned (may be null when count = 0); out [device] one double. count = 0 gives 0.
+ * Errors: IPM_ERR_ARG for a null out, a null x with count > 0, count < 0 or a misaligned x. */
+int ipm_stream_read(ipm_ctx* ctx, const double* x, int64_t count, double* out);
+/* ipm_stream_copy: dst[0, bytes) = src[0, bytes), bit for bit (16-byte non-temporal loads and
+ * stores; the last bytes % 16 bytes one by one). src, dst [device], 16-byte aligned, not
+ * overlapping; bytes = 0 does nothing (null pointers allowed). Errors: IPM_ERR_ARG for null
+ * pointers with bytes > 0, bytes < 0, misalignment or overlap. */
+int ipm_stream_copy(ipm_ctx* ctx, const void* src, void* dst, int64_t bytes);
+
 #define IPM_KERNEL_MATVEC  0   /* the CG matvec pass over A (FP64 accumulation)           */
 #define IPM_KERNEL_SKETCH  1   /* the sketch pass over A                                  */
 #define IPM_KERNEL_GRAM    2   /* the Gram product B B^T                                  */
 #define IPM_KERNEL_MATVEC32 3  /* the mixed form's inner CG matvec (FP32 accumulation)   */
 #define IPM_KERNEL_RESID64 4   /* the mixed form's FP64-accumulated residual pass          */
-#define IPM_KERNEL_COUNT   5
+#define IPM_KERNEL_STREAM_READ 5  /* the read pass of ipm_stream_read                       */
+#define IPM_KERNEL_STREAM_COPY 6  /* the copy pass of ipm_stream_copy                       */
+#define IPM_KERNEL_COUNT   7
 
 /* Per-kernel timing with HIP events recorded at the start and end of launches of the kernels
  * above on the context's stream: on = 0 disables it; on = N >= 1 times every N-th launch of each

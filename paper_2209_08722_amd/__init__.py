@@ -19,7 +19,7 @@ from .native import (IPM_BF16, IPM_CONVERGED, IPM_CSR, IPM_F32, IPM_F64, IPM_MIX
 
 __all__ = ["IpmError", "Context", "Matrix", "SparseMatrix", "Problem", "State", "Params", "ipm_sketch",
            "ipm_sketch_gaussian", "ipm_precond_factor", "ipm_pcg_solve", "ipm_step", "ipm_step_warm", "ipm_last_dy",
-           "ipm_normal_matvec", "solve", "IPM_OK", "IPM_CONVERGED", "IPM_F64", "IPM_F32", "IPM_BF16",
+           "ipm_normal_matvec", "ipm_stream_read", "ipm_stream_copy", "solve", "IPM_OK", "IPM_CONVERGED", "IPM_F64", "IPM_F32", "IPM_BF16",
            "IPM_CSR", "IPM_PLAIN", "IPM_MIXED", "IPM_MIXED_F32ACC", "IPM_WARM_NONE", "IPM_WARM_PREV", "IPM_WARM_GIVEN"]
 
 
@@ -255,6 +255,30 @@ def ipm_normal_matvec(ctx: Context, A: Matrix, d2, v):
     Ac = A.c()
     ctx.check(ctx.lib.ipm_normal_matvec(ctx.h, ctypes.byref(Ac), _ptr(d2), _ptr(v), _ptr(q)))
     return q
+
+
+def ipm_stream_read(ctx: Context, x, out=None):
+    """FP64 sum of the contiguous FP64 tensor x in one streaming pass (bandwidth probe); returns
+    a one-element device tensor (or fills `out`)."""
+    torch = _torch()
+    _need_dev(x, "x", torch.float64)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x.device)
+    ctx.check(ctx.lib.ipm_stream_read(ctx.h, _ptr(x), x.numel(), _ptr(out)))
+    return out
+
+
+def ipm_stream_copy(ctx: Context, src, dst, nbytes: Optional[int] = None):
+    """dst's first nbytes bytes (default: all of src) = src's, in one streaming pass (bandwidth
+    probe); both contiguous device tensors."""
+    _need_dev(src, "src")
+    _need_dev(dst, "dst")
+    size = src.numel() * src.element_size()
+    nbytes = size if nbytes is None else int(nbytes)
+    if nbytes > size or nbytes > dst.numel() * dst.element_size():
+        raise ValueError("nbytes exceeds a buffer")
+    ctx.check(ctx.lib.ipm_stream_copy(ctx.h, _ptr(src), _ptr(dst), nbytes))
+    return dst
 
 
 def ipm_sketch(ctx: Context, A: Matrix, d, seed: int, k: int, w: int, s: int, out_dtype=None):

@@ -19,7 +19,7 @@ LIB = os.path.join(PKG, "libipmsk.so")
 ARCH = "gfx950"
 
 SOURCES = ["strip.hip", "sparse.hip", "dense.hip", "gauss.hip", "pcg.hip", "sketch.hip", "step.hip", "mlp.hip",
-           "ipmsk.cpp"]
+           "probe.hip", "ipmsk.cpp"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

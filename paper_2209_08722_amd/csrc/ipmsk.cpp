@@ -22,7 +22,7 @@ namespace {
 enum WsId {
     W_PART = 0, W_COLPART, W_RED, W_D2, W_RD, W_DS, W_DX, W_RP, W_P, W_DY, W_RHAT, W_G1, W_G2, W_U, W_B,
     W_L, W_X, W_XT, W_T, W_SCAL, W_PCG_VEC, W_PCG_RHO, W_PCG_CD, W_PCG_CI, W_STATUS, W_PART3, W_PARTMIN,
-    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_MLPF, W_MLPD, W_MLPI, W_WQ, W_COEF, W_GU, W_COUNT
+    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_MLPF, W_MLPD, W_MLPI, W_WQ, W_COEF, W_GU, W_STREAM, W_COUNT
 };
 
 struct TimedPair {
@@ -1015,6 +1015,36 @@ int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const
     if (!d2 || !v || !q) return fail(ctx, IPM_ERR_ARG, "null pointer");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
     CHK(matvec_pass(ctx, A, d2, v, q, nullptr, -1));
+    return IPM_OK;
+}
+
+int ipm_stream_read(ipm_ctx* ctx, const double* x, int64_t count, double* out) {
+    if (!ctx) return IPM_ERR_ARG;
+    if (count < 0) return fail(ctx, IPM_ERR_ARG, "count < 0");
+    if ((!x && count > 0) || !out) return fail(ctx, IPM_ERR_ARG, "null pointer");
+    if (reinterpret_cast<uintptr_t>(x) % 16 != 0) return fail(ctx, IPM_ERR_ARG, "x is not 16-byte aligned");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    double* part;
+    CHK(ws(ctx, W_STREAM, (size_t)stream_read_parts(count, ctx->num_cu), &part));
+    Timer t(ctx, IPM_KERNEL_STREAM_READ);
+    HIPCHK(launch_stream_read(x, count, part, out, ctx->num_cu, ctx->stream));
+    t.stop();
+    return IPM_OK;
+}
+
+int ipm_stream_copy(ipm_ctx* ctx, const void* src, void* dst, int64_t bytes) {
+    if (!ctx) return IPM_ERR_ARG;
+    if (bytes < 0) return fail(ctx, IPM_ERR_ARG, "bytes < 0");
+    if (bytes == 0) return IPM_OK;
+    if (!src || !dst) return fail(ctx, IPM_ERR_ARG, "null pointer");
+    const uintptr_t s = reinterpret_cast<uintptr_t>(src), d = reinterpret_cast<uintptr_t>(dst);
+    if (s % 16 != 0 || d % 16 != 0) return fail(ctx, IPM_ERR_ARG, "src or dst is not 16-byte aligned");
+    if (bytes > 0 && s < d + (uintptr_t)bytes && d < s + (uintptr_t)bytes)
+        return fail(ctx, IPM_ERR_ARG, "src and dst overlap");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    Timer t(ctx, IPM_KERNEL_STREAM_COPY);
+    HIPCHK(launch_stream_copy(src, dst, bytes, ctx->num_cu, ctx->stream));
+    t.stop();
     return IPM_OK;
 }
 

@@ -135,6 +135,12 @@ hipError_t launch_diag_sum(const double* A, int m, int lda, double* out, hipStre
 hipError_t launch_diag_add(double* A, int m, int lda, double delta, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st);
 
+// Bandwidth probes (probe.hip). stream_read_parts: the number of partials launch_stream_read writes.
+int stream_read_parts(int64_t count, int num_cu);
+hipError_t launch_stream_read(const double* x, int64_t count, double* part, double* out, int num_cu,
+                              hipStream_t st);
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, int num_cu, hipStream_t st);
+
 // ---- PCG -----------------------------------------------------------------------------------------
 enum PcgInt { PI_DONE = 0, PI_STATUS, PI_ITERS, PI_WARM, PI_COUNT = 8 };
 enum PcgDbl { PD_RHO0 = 0, PD_RHO1, PD_RHOSTAR, PD_HIST = 8 };

@@ -28,6 +28,7 @@ IPM_ERR_NOMEM = -6
 IPM_F64, IPM_F32, IPM_BF16 = 0, 1, 2
 IPM_DENSE_ROWMAJOR, IPM_CSR = 0, 1
 IPM_KERNEL_MATVEC, IPM_KERNEL_SKETCH, IPM_KERNEL_GRAM, IPM_KERNEL_MATVEC32, IPM_KERNEL_RESID64 = 0, 1, 2, 3, 4
+IPM_KERNEL_STREAM_READ, IPM_KERNEL_STREAM_COPY = 5, 6
 IPM_PLAIN, IPM_MIXED, IPM_MIXED_F32ACC = 0, 1, 2
 IPM_WARM_NONE, IPM_WARM_PREV, IPM_WARM_GIVEN = 0, 1, 2
 
@@ -106,6 +107,8 @@ SIGNATURES = [
                               c_int32, POINTER(IpmStepInfo)]),
     ("ipm_last_dy", c_int, [c_void_p, c_int64, c_void_p]),
     ("ipm_normal_matvec", c_int, [c_void_p, POINTER(IpmMatrix), c_void_p, c_void_p, c_void_p]),
+    ("ipm_stream_read", c_int, [c_void_p, c_void_p, c_int64, c_void_p]),
+    ("ipm_stream_copy", c_int, [c_void_p, c_void_p, c_void_p, c_int64]),
     ("ipm_mlp_param_count", c_int64, [c_int32, c_int32, c_int32]),
     ("ipm_mlp_features", c_int, [c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_int64,
                                  c_void_p]),
