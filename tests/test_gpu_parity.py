@@ -86,7 +86,12 @@ def test_normal_matvec_low_storage(ctx, m, n, dtype):
 @pytest.mark.parametrize("m,n,w,s,seed,k", [(50, 2000, 200, 1, 0, 0), (37, 1001, 96, 3, 5, 7),
                                             (5, 40, 12, 3, 11, 4), (64, 5000, 256, 8, 2, 1),
                                             (500, 20000, 2000, 2, 9, 3), (3, 17, 4, 2, 1, 0),
-                                            (20, 5000, 48000, 2, 3, 1), (7, 3001, 30000, 3, 2, 0)])
+                                            (20, 5000, 48000, 2, 3, 1), (7, 3001, 30000, 3, 2, 0),
+                                            # column chunks added atomically: two rows per block with an
+                                            # odd last row block; one row per block at two and at one
+                                            # block per CU (w = 6000 and 12000); short last chunks
+                                            (101, 30001, 4000, 2, 4, 2), (60, 50001, 6000, 2, 7, 1),
+                                            (30, 40000, 12000, 3, 1, 0)])
 def test_sketch_parity(ctx, m, n, w, s, seed, k):
     A = rand_lp_matrix(m, n, 100 + m)
     rng = np.random.default_rng(3)
