@@ -215,7 +215,9 @@ int do_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* dvals, int is_d2,
         if (out_f64) {
             HIPCHK(launch_fill(reinterpret_cast<double*>(B), (int64_t)m * w, 0.0, ctx->stream));
         } else {
-            HIPCHK(hipMemsetAsync(B, 0, (size_t)m * w * sizeof(float), ctx->stream));
+            // FP32 zero is all-zero bits: cleared by the integer fill kernel (a kernel, not a
+            // memset, so the call can be captured in a HIP graph)
+            HIPCHK(launch_fill_i32(reinterpret_cast<int*>(B), (int64_t)m * w, 0, ctx->stream));
         }
     }
     Timer t(ctx, IPM_KERNEL_SKETCH);
