@@ -29,10 +29,10 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 
 WORKLOADS = {
-    "1": dict(cfg=1, m=500, n=100_000, w=2000, s=2, seed=0,
+    "dense_500x100000": dict(m=500, n=100_000, w=2000, s=2, seed=0,
               desc="dense 500x100000 FP64 LP (A iid N(0,1), feasible/bounded generator), "
                    "sparse embedding w=2000 s=2, PCG tol 1e-10, to gap 1e-8"),
-    "0": dict(cfg=0, m=50, n=2000, w=200, s=1, seed=0,
+    "dense_50x2000": dict(m=50, n=2000, w=200, s=1, seed=0,
               desc="dense 50x2000 FP64 LP, CountSketch w=200 s=1, PCG tol 1e-10, to gap 1e-8"),
 }
 
@@ -220,7 +220,7 @@ def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
     import torch
     from lpgen import device as gdev
     from paper_2209_08722_amd import learned as L
-    if which == "3":
+    if which == "illcond_2000x200000":
         m, n, w, s, storage = 2000, 200_000, 8000, 2, "f32"
         make = lambda sd: gdev.illcond_lp(m, n, seed=sd, storage=storage)
         desc = ("ill-conditioned A = U diag(sigma) V^T, 2000x200000, sigma log-spaced 1..1e4, FP32 storage "
@@ -423,12 +423,13 @@ def main() -> int:
     # solves timed, so the rate is the whole-solve average rather than that of a phase of it
     ap.add_argument("--steps", type=int, default=96)
     ap.add_argument("--warmup", type=int, default=48)
-    ap.add_argument("--workload", default="1", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="dense_500x100000", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the Algorithm 2 comparison and the v-correction ablation")
-    ap.add_argument("--forms", default="3", choices=["3", "4d", "none"],
+    ap.add_argument("--forms", default="illcond_2000x200000",
+                    choices=["illcond_2000x200000", "dense_2000x2000000", "none"],
                     help="workload of the plain vs mixed+learned comparison")
     ap.add_argument("--train-seeds", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=100)
@@ -472,7 +473,7 @@ def main() -> int:
 
     wl = WORKLOADS[args.workload]
     log(f"generating workload {args.workload}: {wl['desc']}")
-    lp = lpgen.config(wl["cfg"], seed=wl["seed"])
+    lp = lpgen.workload(args.workload, seed=wl["seed"])
     m, n, w, s = lp.m, lp.n, wl["w"], wl["s"]
     ctx = P.Context(0)
     prob = P.Problem.from_lp(lp)

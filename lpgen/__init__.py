@@ -27,8 +27,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["LP", "dense_lp", "sparse_lp", "svm_lp", "tiny_lp", "config", "bf16_round", "f32_round",
-           "CONFIGS", "SVM_SHAPES", "mlp_init"]
+__all__ = ["LP", "dense_lp", "sparse_lp", "svm_lp", "tiny_lp", "workload", "bf16_round", "f32_round",
+           "WORKLOADS", "SVM_SHAPES", "mlp_init"]
 
 
 @dataclass
@@ -185,30 +185,32 @@ def illcond_lp(m: int, n: int, seed: int = 0, matrix_seed: int = 1000,
     return LP(A, b, c, x0, y0, s0, storage=storage, name=f"illcond{m}x{n}s{seed}")
 
 
-# Workload table: (m, n, storage, sketch width w, nonzeros per sketch row s, seeds)
-CONFIGS = {
-    0: dict(m=50, n=2000, storage="f64", w=200, s=1, seeds=[0]),
-    1: dict(m=500, n=100_000, storage="f64", w=2000, s=2, seeds=[0, 1, 2, 3, 4]),
-    2: dict(m=1000, n=1_000_000, storage="bf16", w=4000, s=2, seeds=[0], density=1e-3),
-    3: dict(m=2000, n=200_000, storage="f32", w=8000, s=2, seeds=list(range(80))),
-    "4d": dict(m=2000, n=2_000_000, storage="bf16", w=16000, s=2, seeds=[0]),
-    "4s": dict(m=5000, n=2_000_000, storage="bf16", w=40000, s=2, seeds=[0], density=5e-4),
+# Workload table: (kind, m, n, storage, sketch width w, nonzeros per sketch row s, seeds)
+WORKLOADS = {
+    "dense_50x2000": dict(kind="dense", m=50, n=2000, storage="f64", w=200, s=1, seeds=[0]),
+    "dense_500x100000": dict(kind="dense", m=500, n=100_000, storage="f64", w=2000, s=2, seeds=[0, 1, 2, 3, 4]),
+    "csr_1000x1000000": dict(kind="csr", m=1000, n=1_000_000, storage="bf16", w=4000, s=2, seeds=[0],
+                             density=1e-3),
+    "illcond_2000x200000": dict(kind="illcond", m=2000, n=200_000, storage="f32", w=8000, s=2,
+                                seeds=list(range(80))),
+    "dense_2000x2000000": dict(kind="dense", m=2000, n=2_000_000, storage="bf16", w=16000, s=2, seeds=[0]),
+    "csr_5000x2000000": dict(kind="csr", m=5000, n=2_000_000, storage="bf16", w=40000, s=2, seeds=[0],
+                             density=5e-4),
 }
 
 
-def config(i, seed: Optional[int] = None) -> LP:
-    """Build workload ``i`` (0, 1, 2, 3, "4d" or "4s") at ``seed`` (defaults to its first seed)."""
-    cfg = CONFIGS[i]
+def workload(name: str, seed: Optional[int] = None) -> LP:
+    """Build the named workload (a key of WORKLOADS) at ``seed`` (defaults to its first seed)."""
+    cfg = WORKLOADS[name]
     sd = cfg["seeds"][0] if seed is None else seed
-    if i == 3:
+    if cfg["kind"] == "illcond":
         lp = illcond_lp(cfg["m"], cfg["n"], seed=sd, storage=cfg["storage"])
-    elif "density" in cfg:
+    elif cfg["kind"] == "csr":
         lp = sparse_lp(cfg["m"], cfg["n"], cfg["density"], seed=sd, storage=cfg["storage"],
-                       name=f"cfg{i}s{sd}")
+                       name=f"{name}_s{sd}")
     else:
-        lp = dense_lp(cfg["m"], cfg["n"], seed=sd, storage=cfg["storage"],
-                      name=f"cfg{i}s{sd}")
-    lp.meta.update(w=cfg["w"], s=cfg["s"], config=i, seed=sd)
+        lp = dense_lp(cfg["m"], cfg["n"], seed=sd, storage=cfg["storage"], name=f"{name}_s{sd}")
+    lp.meta.update(w=cfg["w"], s=cfg["s"], workload=name, seed=sd)
     return lp
 
 

@@ -100,7 +100,7 @@ def test_chebyshev_solve_matches_highs(ctx, m, n, sparse):
 
 
 def test_chebyshev_full_size(ctx):
-    lp = lpgen.config(1, seed=0)
+    lp = lpgen.workload("dense_500x100000", seed=0)
     prob = P.Problem.from_lp(lp)
     ch = P.solve(ctx, prob, P.Params(w=2000, s=2, seed=0, solver=1))
     cg = P.solve(ctx, prob, P.Params(w=2000, s=2, seed=0))

@@ -106,7 +106,7 @@ def test_feasible_solve_matches_highs(ctx, m, n, sparse):
 def test_feasible_against_infeasible_full_size(ctx):
     """Algorithm 2 from the witness pair and Algorithm 3 from x = s = 1, y = 0 on the
     500 x 100000 workload reach the same optimum."""
-    lp = lpgen.config(1, seed=0)
+    lp = lpgen.workload("dense_500x100000", seed=0)
     prob = P.Problem.from_lp(lp)
     feas = P.solve(ctx, prob, P.Params(w=2000, s=2, seed=0, feasible=1), st=_gpu_state(_start(lp)))
     infeas = P.solve(ctx, prob, P.Params(w=2000, s=2, seed=0))

@@ -119,7 +119,7 @@ def test_gaussian_solve_matches_highs(ctx, m, n, precision):
 def test_gaussian_full_size(ctx):
     """500 x 100000 (the bench workload), w = 2000: sampled rows of the sketch against the oracle,
     and the Gaussian-sketch solve against the sparse-embedding solve and the host KKT check."""
-    lp = lpgen.config(1, seed=0)
+    lp = lpgen.workload("dense_500x100000", seed=0)
     prob = P.Problem.from_lp(lp)
     rng = np.random.default_rng(3)
     d = np.exp(rng.uniform(-3, 3, lp.n))

@@ -258,7 +258,7 @@ def _lockstep(ctx, lp, oprm, gprm, steps, rtol_state):
 
 
 def test_step_lockstep_config0(ctx):
-    lp = lpgen.config(0)
+    lp = lpgen.workload("dense_50x2000")
     oprm = oipm.Params(w=200, s=1, seed=0)
     _lockstep(ctx, lp, oprm, P.Params(w=200, s=1, seed=0), steps=12, rtol_state=1e-8)
 
@@ -299,7 +299,7 @@ def test_redraw_rule_matches_oracle(ctx, near):
 
 
 def test_solve_config0_matches_oracle(ctx):
-    lp = lpgen.config(0)
+    lp = lpgen.workload("dense_50x2000")
     res = P.solve(ctx, P.Problem.from_lp(lp), P.Params(w=200, s=1, seed=0))
     ores = oipm.solve(lp.A, lp.b, lp.c, oipm.Params(w=200, s=1, seed=0), "sketch")
     assert res.converged and ores.converged
@@ -406,7 +406,7 @@ def test_method_option_errors(ctx):
 def test_config1_full_size_lockstep_and_solve(ctx):
     """The bench workload (500 x 100000, w = 2000, s = 2): two lockstep steps against the
     oracle, then the full GPU solve against the oracle's direct-solver IPM optimum."""
-    lp = lpgen.config(1, seed=0)
+    lp = lpgen.workload("dense_500x100000", seed=0)
     oprm = oipm.Params(w=2000, s=2, seed=0)
     _lockstep(ctx, lp, oprm, P.Params(w=2000, s=2, seed=0), steps=2, rtol_state=1e-9)
     res = P.solve(ctx, P.Problem.from_lp(lp), P.Params(w=2000, s=2, seed=0))

@@ -229,7 +229,7 @@ def test_sparse_argument_errors(ctx):
 @pytest.fixture(scope="module")
 def lp2():
     print("\ngenerating the 1000 x 1e6 sparse LP (density 1e-3, BF16 values)", flush=True)
-    lp = lpgen.config(2)
+    lp = lpgen.workload("csr_1000x1000000")
     print("oracle direct-solver IPM on it", flush=True)
     ores = oipm.solve(lp.A, lp.b, lp.c, oipm.Params(), "exact")
     assert ores.converged
@@ -282,7 +282,7 @@ def test_config2_full_size_solves(ctx, lp2):
 @pytest.fixture(scope="module")
 def lp4s():
     print("\ngenerating the 5000 x 2e6 sparse LP (density 5e-4, BF16 values)", flush=True)
-    return lpgen.config("4s")
+    return lpgen.workload("csr_5000x2000000")
 
 
 def test_config4s_full_size_matvec_and_sketch(ctx, lp4s):

@@ -526,7 +526,7 @@ def test_optimum_closed_form_square():
 
 def test_config0_matches_highs_and_duality_sandwich():
     """Objective of the 50 x 2000 workload vs scipy's HiGHS; b^T y0 <= opt <= c^T x0."""
-    lp = lpgen.config(0)
+    lp = lpgen.workload("dense_50x2000")
     ref = linprog(lp.c, A_eq=lp.A, b_eq=lp.b, bounds=(0, None), method="highs")
     assert ref.status == 0
     opt = ref.fun
