@@ -69,9 +69,12 @@ typedef struct ipm_ctx ipm_ctx;
  *   are trusted: row_ptr / col_ptr must be non-decreasing from 0 to nnz and every index in
  *   range (an index out of range is an out-of-bounds device access, not a returned error).
  *   Duplicate entries are summed; the order within a row or column is free.
- * Sizes: 1 <= m <= n. A dense A keeps a column strip of all m rows on chip in its passes, so
- *   m <= 2048 with IPM_F64 or IPM_F32 values and m <= 6400 with IPM_BF16 values; a CSR A allows
- *   m <= 2^20 and n < 2^31. Larger sizes are IPM_ERR_ARG, reported before any device work. */
+ * Sizes: 1 <= m <= n and m <= 10236 for every layout (the CG kernels keep two FP64 m-vectors
+ *   in one block's 160 KB of LDS). A dense A keeps a column strip of all m rows on chip in its
+ *   passes, so m <= 2048 with IPM_F64 or IPM_F32 values and m <= 6400 with IPM_BF16 values, and
+ *   a thread addresses the rows of its row group (64 rows) with a 32-bit element offset, so
+ *   63*ld + 128/elem_size must stay below 2^32 (ld below about 6.8e7 elements). A CSR A needs
+ *   n < 2^31. Larger sizes are IPM_ERR_ARG, reported before any device work. */
 typedef struct {
     int64_t m, n, ld;
     int32_t layout;          /* IPM_DENSE_ROWMAJOR | IPM_CSR */
@@ -124,10 +127,11 @@ typedef struct {
     int32_t vcorr;       /* 1: perturbation v of eq. compv; 0: v = 0                         */
     int32_t precision;   /* A is read in its storage type (F64, F32 or BF16) by every form.
                             IPM_PLAIN: FP64 accumulation everywhere, B stored FP64.
-                            IPM_MIXED: the sketch accumulates in FP32 and B is stored FP32
-                            (the Gram widens it to an FP64 Q); the CG matvecs accumulate in
-                            FP64, which costs nothing on these bandwidth-bound passes and
-                            keeps the plain form's CG iteration counts.
+                            IPM_MIXED: the sketch accumulates in FP64 (LDS buckets) and B is
+                            stored rounded to FP32 (the Gram widens it to an FP64 Q); the CG
+                            matvecs accumulate in FP64, which costs nothing on these
+                            bandwidth-bound passes and keeps the plain form's CG iteration
+                            counts.
                             IPM_MIXED_F32ACC: as IPM_MIXED, and the CG runs as iterative
                             refinement: inner CG with FP32-accumulated matvecs to inner_tol,
                             outer residual p - A D^2 A^T dy recomputed with FP64 accumulation,
@@ -239,7 +243,9 @@ int ipm_sketch_gaussian(ipm_ctx* ctx, const ipm_matrix* A, const double* d, uint
  *   L    [device] m x m, or NULL; on return its lower triangle holds L (upper part unspecified)
  *   Linv [device] m x m; on return the lower triangle holds L^{-1}, the upper part is zero
  *   bad_pivot  [host] may be NULL; set to the first failing pivot index or -1.
- * Errors: IPM_ERR_NOT_SPD if a pivot is not positive (B lacks full row rank). Synchronizes. */
+ * Errors: IPM_ERR_ARG unless 1 <= m <= 10236 (the row limit of every entry point), w >= 1 and
+ *   B, Linv are set; IPM_ERR_NOT_SPD if a pivot is not positive (B lacks full row rank).
+ *   Synchronizes. */
 int ipm_precond_factor(ipm_ctx* ctx, int64_t m, int32_t w, int32_t b_dtype, const void* B,
                        double* L, double* Linv, int64_t* bad_pivot);
 

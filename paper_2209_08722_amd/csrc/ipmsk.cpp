@@ -56,6 +56,9 @@ struct ipm_ctx {
 namespace {
 
 constexpr size_t kPinnedBytes = 4096;
+// Largest m of any entry point: the CG kernels hold two FP64 m-vectors in one block's LDS
+// (160 KB, less the per-wave reduction slots).
+constexpr int64_t kMaxRows = (160 * 1024 - 64) / 16;
 
 int fail(ipm_ctx* ctx, int code, const char* fmt, ...) {
     char buf[512];
@@ -172,7 +175,9 @@ int check_matrix(ipm_ctx* ctx, const ipm_matrix* A) {
     if (!es) return fail(ctx, IPM_ERR_ARG, "unsupported dtype %d", A->dtype);
     if (A->m < 1 || A->n < 1 || A->m > A->n) return fail(ctx, IPM_ERR_ARG, "need 1 <= m <= n (m=%lld n=%lld)",
                                                           (long long)A->m, (long long)A->n);
-    if (A->m > 1 << 20) return fail(ctx, IPM_ERR_ARG, "m too large");
+    if (A->m > kMaxRows)
+        return fail(ctx, IPM_ERR_ARG, "m=%lld exceeds the limit of %lld rows (the CG kernels keep two m-vectors in LDS)",
+                    (long long)A->m, (long long)kMaxRows);
     if (!A->val) return fail(ctx, IPM_ERR_ARG, "A->val is null");
     if (A->layout == IPM_CSR) {
         if (A->n >= ((int64_t)1 << 31)) return fail(ctx, IPM_ERR_ARG, "n too large for 32-bit column indices");
@@ -184,9 +189,16 @@ int check_matrix(ipm_ctx* ctx, const ipm_matrix* A) {
     if (A->ld < A->n) return fail(ctx, IPM_ERR_ARG, "ld < n");
     if ((A->ld * es) % 16 != 0) return fail(ctx, IPM_ERR_ARG, "ld*elem_size must be a multiple of 16 bytes");
     if (reinterpret_cast<uintptr_t>(A->val) % 16 != 0) return fail(ctx, IPM_ERR_ARG, "A->val must be 16-byte aligned");
-    if (strip_plan(A->dtype, (int)A->m, A->n, ctx->num_cu, STRIP_MATVEC).nt <= 0)
+    const StripPlan pl = strip_plan(A->dtype, (int)A->m, A->n, ctx->num_cu, STRIP_MATVEC);
+    if (pl.nt <= 0)
         return fail(ctx, IPM_ERR_ARG, "m=%lld exceeds the dense passes' limit (%d rows with %s values)",
                     (long long)A->m, A->dtype == IPM_BF16 ? 6400 : 2048, A->dtype == IPM_BF16 ? "BF16" : "FP64/FP32");
+    // the strip passes address a thread's rows inside a row group with a 32-bit element offset
+    const int64_t rg = pl.nt / pl.lpr;
+    if ((rg - 1) * A->ld + pl.sw > (int64_t)UINT32_MAX)
+        return fail(ctx, IPM_ERR_ARG, "ld=%lld too large for the dense passes (at most %lld elements per row at m=%lld)",
+                    (long long)A->ld, (long long)(((int64_t)UINT32_MAX - pl.sw) / (rg > 1 ? rg - 1 : 1)),
+                    (long long)A->m);
     return IPM_OK;
 }
 
@@ -963,7 +975,8 @@ int ipm_precond_factor(ipm_ctx* ctx, int64_t m, int32_t w, int32_t b_dtype, cons
                        int64_t* bad_pivot) {
     if (!ctx) return IPM_ERR_ARG;
     if (bad_pivot) *bad_pivot = -1;
-    if (m < 1 || m > 65536 || w < 1 || !B || !Linv) return fail(ctx, IPM_ERR_ARG, "bad arguments");
+    if (m < 1 || m > kMaxRows || w < 1 || !B || !Linv)
+        return fail(ctx, IPM_ERR_ARG, "bad arguments (need 1 <= m <= %lld, w >= 1, B and Linv set)", (long long)kMaxRows);
     if (b_dtype != IPM_F64 && b_dtype != IPM_F32) return fail(ctx, IPM_ERR_ARG, "B must be F64 or F32");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
     double* Lw = L;

@@ -417,3 +417,38 @@ def test_config1_full_size_lockstep_and_solve(ctx):
     oobj = float(lp.c @ ores.state.x)
     assert abs(obj - oobj) <= 1e-8 * (1 + abs(oobj))
     assert abs(res.iterations - (len(ores.infos) - 1)) <= 2
+
+
+def test_dense_ld_limit_rejected_before_device_work(ctx):
+    """The strip passes address the rows of a 64-row (here 32-row) group with a 32-bit element
+    offset: a dense A whose row stride would overflow it is IPM_ERR_ARG before any device access
+    (the descriptor points at a 16-byte aligned one-element buffer, never read)."""
+    import ctypes
+    buf = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+    d2 = torch.ones(4, dtype=torch.float64, device="cuda:0")
+    m = 100                                      # 256-thread blocks, 32 rows per group
+    # FP64 strips are 16 columns wide: 31 ld + 16 must stay below 2^32
+    ld = ((1 << 32) - 1 - 16) // 31 + 1
+    ld += ld % 2                                 # a 16-byte multiple, so only the offset limit fails
+    assert 31 * ld + 16 > (1 << 32) - 1 and 31 * (ld - 2) + 16 <= (1 << 32) - 1
+    Ac = P.native.IpmMatrix(m, ld, ld, 0, 0, buf.data_ptr())
+    rc = ctx.lib.ipm_normal_matvec(ctx.h, ctypes.byref(Ac), buf.data_ptr(), d2.data_ptr(), d2.data_ptr())
+    assert rc == -1 and "ld=" in ctx.lib.ipm_last_error(ctx.h).decode()
+
+
+def test_row_limit_of_the_cg_kernels(ctx):
+    """m above the CG kernels' LDS limit (two FP64 m-vectors per block) is IPM_ERR_ARG for a CSR
+    A and for the factor, before device work."""
+    import ctypes
+    m, n = 10237, 10240
+    z64 = torch.zeros(m + 1, dtype=torch.int64, device="cuda:0")
+    zc = torch.zeros(n + 1, dtype=torch.int64, device="cuda:0")
+    zi = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    v = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    Ac = P.native.IpmMatrix(m, n, 0, 1, 0, v.data_ptr(), 0, z64.data_ptr(), zi.data_ptr(), v.data_ptr(),
+                            zc.data_ptr(), zi.data_ptr())
+    rc = ctx.lib.ipm_normal_matvec(ctx.h, ctypes.byref(Ac), v.data_ptr(), v.data_ptr(), v.data_ptr())
+    assert rc == -1 and "limit" in ctx.lib.ipm_last_error(ctx.h).decode()
+    bad = ctypes.c_int64(0)
+    rc = ctx.lib.ipm_precond_factor(ctx.h, m, m, 0, v.data_ptr(), None, v.data_ptr(), ctypes.byref(bad))
+    assert rc == -1
