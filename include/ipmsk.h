@@ -355,6 +355,22 @@ int ipm_mlp_predict(ipm_ctx* ctx, const ipm_mlp* net, int64_t n, const double* d
 int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v,
                       double* q);
 
+/* ipm_normal_matvec for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * result bit for bit, with the pass's per-block partial sums in a static 16 MB device array
+ * instead of a context workspace. The call allocates and frees nothing.
+ *   A, d2, v, q  as for ipm_normal_matvec (caller-owned, [device]).
+ *   Scratch need: dense A  8 * (G m + G + ceil(m/4)) bytes, G <= 2 * CUs the pass's blocks
+ *                 (at most about 4.2 MB for FP64/FP32 up to 2048 rows);
+ *                 CSR A    8 * (n + ceil(n/256 capped at 2048) + ceil(m/4)) bytes.
+ *   A need above 16 MB (BF16 A with more than about 4000 rows, CSR A with about 2 million or
+ *   more columns) is IPM_ERR_ARG, before device work.
+ * Every call on one GPU shares that GPU's array and leaves its partial sums there; calls that
+ * overlap on one GPU (two streams, two contexts or two host threads at once) race and give
+ * wrong results. Calls ordered on one stream are safe. */
+int ipm_normal_matvec_noalloc(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v,
+                              double* q);
+
 /* Attainable-bandwidth probes: the measured denominators, beside the vendor's 8 TB/s, for the
  * streaming passes over A (the matvec, the sketch, the residual and direction passes). Not
  * steps of the method; both run on the context's stream and use its access pattern (contiguous

@@ -257,6 +257,20 @@ def ipm_normal_matvec(ctx: Context, A: Matrix, d2, v):
     return q
 
 
+def ipm_normal_matvec_noalloc(ctx: Context, A, d2, v, q):
+    """q = A diag(d2) A^T v into the caller's q, with the library allocating nothing (its partial
+    sums in the static scratch array)."""
+    torch = _torch()
+    _need_dev(d2, "d2", torch.float64)
+    _need_dev(v, "v", torch.float64)
+    _need_dev(q, "q", torch.float64)
+    if q.numel() != A.m or v.numel() != A.m or d2.numel() != A.n:
+        raise ValueError("need v, q of length m and d2 of length n")
+    Ac = A.c()
+    ctx.check(ctx.lib.ipm_normal_matvec_noalloc(ctx.h, ctypes.byref(Ac), _ptr(d2), _ptr(v), _ptr(q)))
+    return q
+
+
 def ipm_stream_read(ctx: Context, x, out=None):
     """FP64 sum of the contiguous FP64 tensor x in one streaming pass (bandwidth probe); returns
     a one-element device tensor (or fills `out`)."""

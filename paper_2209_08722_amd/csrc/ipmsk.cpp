@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -51,6 +52,7 @@ struct ipm_ctx {
     int last_inner_iters = 8;  // the same for the inner solves of the mixed form
     int last_cheb_steps = 0;   // Chebyshev steps of the previous solve (first batch after the probe)
     int64_t prev_m = 0;        // length of the accepted dy kept in W_PREV (0: none)
+    double* scratch = nullptr; // this device's copy of the static scratch array (device address)
 };
 
 namespace {
@@ -59,6 +61,34 @@ constexpr size_t kPinnedBytes = 4096;
 // Largest m of any entry point: the CG kernels hold two FP64 m-vectors in one block's LDS
 // (160 KB, less the per-wave reduction slots).
 constexpr int64_t kMaxRows = (160 * 1024 - 64) / 16;
+
+// Static scratch of the allocation-free matvec (ipm_normal_matvec_noalloc): the pass's per-block
+// partial sums live here instead of in a context workspace. Every GPU the library runs on holds
+// its own copy (16 MB) until the process ends. In host code the name is only a symbol: the
+// device address of each GPU's copy is taken once with hipGetSymbolAddress and used from then on.
+constexpr size_t kScratchDoubles = (size_t)2 << 20;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's scratch address (device must be current); taken once per device.
+int scratch_address(int device, double** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return IPM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return IPM_ERR_HIP;
+        }
+        g_scratch_ptr[device] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return IPM_OK;
+}
 
 int fail(ipm_ctx* ctx, int code, const char* fmt, ...) {
     char buf[512];
@@ -897,6 +927,11 @@ int ipm_ctx_create(ipm_ctx** out, int device, void* hip_stream) {
         delete ctx;
         return IPM_ERR_HIP;
     }
+    if (scratch_address(device, &ctx->scratch) != IPM_OK) {
+        (void)hipHostFree(ctx->pinned);
+        delete ctx;
+        return IPM_ERR_HIP;
+    }
 
     *out = ctx;
     return IPM_OK;
@@ -1030,6 +1065,61 @@ int ipm_normal_matvec(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const
     if (!d2 || !v || !q) return fail(ctx, IPM_ERR_ARG, "null pointer");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
     CHK(matvec_pass(ctx, A, d2, v, q, nullptr, -1));
+    return IPM_OK;
+}
+
+int ipm_normal_matvec_noalloc(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v, double* q) {
+    if (!ctx) return IPM_ERR_ARG;
+    CHK(check_matrix(ctx, A));
+    if (!d2 || !v || !q) return fail(ctx, IPM_ERR_ARG, "null pointer");
+    if (!ctx->scratch) return fail(ctx, IPM_ERR_HIP, "no scratch address for device %d", ctx->device);
+    StripCall c{};
+    c.kind = STRIP_MATVEC;
+    c.acc64 = 1;
+    c.post = POST_PLAIN;
+    c.vec0 = v;
+    c.d2 = d2;
+    c.out0 = q;
+    c.dtype = A->dtype;
+    c.A = A->val;
+    c.m = (int)A->m;
+    c.n = A->n;
+    c.ld = A->ld;
+    // carve the pass's buffers out of the scratch array; every entry the kernels read is written
+    // by the same launch sequence first, so nothing needs clearing
+    const size_t nrow = (size_t)rowsum_blocks(c.m);
+    size_t need = 0;
+    StripPlan pl{};
+    if (A->layout == IPM_CSR) {
+        need = nrow + (size_t)sparse_col_blocks(A->n) + (size_t)A->n;
+    } else {
+        pl = strip_plan(A->dtype, c.m, A->n, ctx->num_cu, STRIP_MATVEC);
+        need = nrow + (size_t)pl.grid + (size_t)pl.grid * (size_t)c.m;
+    }
+    if (need > kScratchDoubles)
+        return fail(ctx, IPM_ERR_ARG, "this matvec needs %zu bytes of scratch, the static scratch holds %zu",
+                    need * sizeof(double), kScratchDoubles * sizeof(double));
+    double* p = ctx->scratch;
+    c.gpart = p;
+    p += nrow;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
+    if (A->layout == IPM_CSR) {
+        c.row_ptr = A->row_ptr;
+        c.col_idx = A->col_idx;
+        c.csc_val = A->csc_val;
+        c.col_ptr = A->col_ptr;
+        c.row_idx = A->row_idx;
+        c.colpart = p;
+        p += sparse_col_blocks(A->n);
+        c.coefs = p;
+        HIPCHK(launch_sparse_pass(c, ctx->stream));
+        return IPM_OK;
+    }
+    c.colpart = p;
+    p += pl.grid;
+    c.part = p;
+    HIPCHK(launch_strip_pass(c, pl, ctx->stream));
+    HIPCHK(launch_strip_rowsum(c, pl, ctx->stream));
     return IPM_OK;
 }
 

@@ -107,6 +107,7 @@ SIGNATURES = [
                               c_int32, POINTER(IpmStepInfo)]),
     ("ipm_last_dy", c_int, [c_void_p, c_int64, c_void_p]),
     ("ipm_normal_matvec", c_int, [c_void_p, POINTER(IpmMatrix), c_void_p, c_void_p, c_void_p]),
+    ("ipm_normal_matvec_noalloc", c_int, [c_void_p, POINTER(IpmMatrix), c_void_p, c_void_p, c_void_p]),
     ("ipm_stream_read", c_int, [c_void_p, c_void_p, c_int64, c_void_p]),
     ("ipm_stream_copy", c_int, [c_void_p, c_void_p, c_void_p, c_int64]),
     ("ipm_mlp_param_count", c_int64, [c_int32, c_int32, c_int32]),
