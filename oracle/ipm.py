@@ -39,6 +39,14 @@ the neighbourhood's residual term uses the exact contraction r(alpha) =
 violated by rounding at alpha = 0 is only kept from getting worse; the stop
 test is relative gap, primal and dual residual all <= gap_tol; CG stops early
 when its preconditioned residual drops by less than 1 % over 10 iterations.
+
+Parity unpinned: two policies here are this implementation's, not the paper's
+(which draws W once per iteration and runs a fixed number of CG steps), and no
+value the paper prints or mathematics fixes pins them: the CG stagnation guard
+above, and the redraw rule (sketch_size, sketch_seed and the loop in step: a
+draw whose CG fails is redrawn with w doubled, s >= 2 and a shifted seed; a
+redrawn W whose Q factors only with a shift is kept). Their tests check the
+oracle's own behaviour and that the GPU follows it.
 """
 from __future__ import annotations
 

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
+import lockstep
 import lpgen
 from oracle import ipm as oipm
 from oracle import sketch as osk
@@ -152,27 +153,17 @@ def test_pcg_mixed_warm_start(ctx):
 # ------------------------------------------------------------------------- mixed IPM
 
 def _lockstep(ctx, lp, oprm, gprm, steps, rtol_state):
+    """Lock-step (tests/lockstep.py) of a mixed form against the FP64 oracle on the same rounded
+    LP. The CG of every form stops on the FP64-accumulated residual at the same tolerance, so dy
+    is held to the plain form's energy-norm bound; B is stored in FP32 (a preconditioner, and a
+    perturbation v, that differ from the oracle's by FP32 rounding), so the step length is held
+    to rtol_state relative and x, s to rtol_state of their update's size. The FP32-accumulated
+    form counts the inner iterations of its refinement rounds, so its CG count is not compared."""
     prob = P.Problem.from_lp(lp, dtype=tdtype(lp.storage))
-    st = oipm.initial_state(lp.A, lp.b, lp.c)
-    worst = 0.0
-    for k in range(steps):
-        gst = P.State(dev(st.x), dev(st.y), dev(st.s), st.k, st.mu0, st.r0norm)
-        ginfo = P.ipm_step(ctx, prob, gst, gprm)
-        new, oinfo = oipm.step(lp.A, lp.b, lp.c, st, oprm, "sketch")
-        for key in ("mu", "relgap", "rp_rel", "rd_rel"):
-            assert ginfo[key] == pytest.approx(getattr(oinfo, key), rel=1e-10, abs=1e-15)
-        if oinfo.status == oipm.CONVERGED:
-            assert ginfo["rc"] == 1
-            break
-        assert ginfo["pcg_relres"] <= oprm.tol_pcg
-        for name in ("x", "y", "s"):
-            g = host(getattr(gst, name))
-            o = getattr(new, name)
-            err = np.linalg.norm(g - o) / np.linalg.norm(o)
-            worst = max(worst, err)
-            assert err <= rtol_state, (k, name, err)
-        st = new
-    print(f"mixed lockstep {lp.name}: worst relative state error {worst:.3e}")
+    recs, _, conv = lockstep.run(P, ctx, lp.A, lp.b, lp.c, prob, oprm, gprm, steps, state_tol=rtol_state,
+                                 alpha_tol=rtol_state, count_check=gprm.precision != P.IPM_MIXED_F32ACC,
+                                 label=f"mixed form {gprm.precision}, {lp.name}")
+    return recs, conv
 
 
 PREC = {"mixed": "IPM_MIXED", "f32acc": "IPM_MIXED_F32ACC"}
@@ -186,7 +177,8 @@ def test_step_lockstep_mixed(ctx, storage, prec):
     gprm = P.Params(w=200, s=2, seed=1, precision=getattr(P, PREC[prec]))
     # both sides solve to the same preconditioned residual; the directions differ by at most
     # that much, amplified by the step's sensitivity, so states agree far below the stop tolerance
-    _lockstep(ctx, lp, oprm, gprm, steps=10, rtol_state=1e-7)
+    _, conv = _lockstep(ctx, lp, oprm, gprm, steps=200, rtol_state=1e-7)
+    assert conv
 
 
 @pytest.mark.parametrize("prec", ["mixed", "f32acc"])
@@ -228,8 +220,8 @@ def test_solve_warm_prev(ctx, precision):
     assert cold.converged and warm.converged
     oc = float(lp.c @ host(cold.state.x))
     ow = float(lp.c @ host(warm.state.x))
-    # both solves stop at relative gap <= 1e-8: each objective within ~1e-8 of the optimum
-    assert abs(oc - ow) <= 2e-8 * (1 + abs(oc))
+    # both are upper bounds of the optimum within their own relative gap (<= 1e-8)
+    assert abs(oc - ow) <= 1e-8 * (1 + abs(oc))
     used = sum(i["warm_used"] for i in warm.infos)
     print(f"{precision}: cold CG {sum(i['pcg_iters'] for i in cold.infos)}, "
           f"prev-warm CG {sum(i['pcg_iters'] for i in warm.infos)}, warm kept in {used} steps")
