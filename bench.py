@@ -2,13 +2,20 @@
 
 One step = one IPM iteration (Algorithm 3): residual pass, sketch, Gram, Cholesky and
 inverse, preconditioned CG to tol 1e-10, direction pass, perturbation v, step lengths and
-update. Inputs are resident in HBM before timing starts. When a solve reaches the stop test
-(relative gap and residuals <= 1e-8) the state is reset to x = s = 1, y = 0 and timing goes
-on, so exactly --steps iterations are timed.
+update. Inputs are resident in HBM before timing starts. The timed window starts at iteration 0
+of a fresh solve (x = s = 1, y = 0); when a solve reaches the stop test (relative gap and
+residuals <= 1e-8) the state is reset to the start and timing goes on, so exactly --steps
+iterations are timed. Beside that window the line carries the whole-solve rate (iterations to
+the stop test over the wall time of complete solves).
 
-Prints one JSON line (rank 0) with the throughput, the roofline record of the CG matvec pass
-(its average duration measured with HIP events on the library's stream during the timed
-region) and the oracle's CPU baseline.
+The default workload is the largest one-GPU dense LP, 2000 x 2*10^6 with A i.i.d. N(0, 1)
+stored in BF16 (8 GB) and an FP64 copy of the same values (32 GB): `value` is the plain FP64
+form's rate, and the same line compares it with the mixed-precision form (BF16 storage) with and
+without the learned warm start on the same LP, each form's result certified on the host in FP64.
+
+Prints one JSON line with the throughput, the roofline record of the CG matvec pass (its average
+duration measured with HIP events on the library's stream during the timed region) and the
+oracle's CPU baseline.
 """
 from __future__ import annotations
 
@@ -29,6 +36,10 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 
 WORKLOADS = {
+    "dense_2000x2000000": dict(m=2000, n=2_000_000, w=16000, s=2, seed=64, device=True, storage="bf16",
+              desc="dense 2000x2000000 LP, A iid N(0,1) stored in BF16 (8 GB) with an FP64 copy of the same "
+                   "values (32 GB) for the plain form, feasible/bounded generator (matrix seed 0, (b, c) seed 64), "
+                   "sparse embedding w=16000 s=2, PCG tol 1e-10, to gap 1e-8"),
     "dense_500x100000": dict(m=500, n=100_000, w=2000, s=2, seed=0,
               desc="dense 500x100000 FP64 LP (A iid N(0,1), feasible/bounded generator), "
                    "sparse embedding w=2000 s=2, PCG tol 1e-10, to gap 1e-8"),
@@ -72,14 +83,42 @@ def traffic_record(workload: str):
         return None
 
 
+def host_info() -> dict:
+    """CPU model, logical CPUs, RAM and the BLAS library NumPy calls (with its thread count)."""
+    info = {"cpu_model": None, "logical_cpus": os.cpu_count(), "ram_gb": None, "blas": None, "blas_threads": None}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["ram_gb"] = round(int(line.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if blas:
+            info["blas"] = f"{blas[0].get('internal_api')} {blas[0].get('version')}"
+            info["blas_threads"] = int(blas[0].get("num_threads", 1))
+    except Exception:
+        pass
+    return info
+
+
+def _baseline_record(it, el, hi, sample):
+    cores = hi.get("blas_threads") or hi.get("logical_cpus") or 1
+    return {"value": it / el, "unit": "IPM iter/s", "cores": int(cores), "kind": "oracle",
+            "sample": sample, "seconds": el, "iterations": it, "cpu_model": hi.get("cpu_model"),
+            "blas": hi.get("blas"), "ram_gb": hi.get("ram_gb"), "logical_cpus": hi.get("logical_cpus")}
+
+
 def cpu_baseline(lp, budget_s: float):
     """The oracle (direct-solver FP64 IPM) on the host cores for about budget_s seconds."""
     from oracle import ipm as oipm
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    hi = host_info()
     st = oipm.initial_state(lp.A, lp.b, lp.c)
     prm = oipm.Params()
     it = 0
@@ -92,19 +131,68 @@ def cpu_baseline(lp, budget_s: float):
         st = new
         it += 1
     el = time.perf_counter() - t0
-    return {"value": it / el, "unit": "IPM iter/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"first {it} iterations of the same LP with the oracle's direct-solver "
-                      f"(dense Cholesky of A D^2 A^T) FP64 IPM, {el:.1f} s wall"}
+    return _baseline_record(it, el, hi, f"first {it} iterations of the same LP with the oracle's direct-solver "
+                                        f"(dense Cholesky of A D^2 A^T) FP64 IPM, {el:.1f} s wall")
+
+
+def cpu_baseline_device_lp(lp, budget_s: float):
+    """The oracle's direct-solver FP64 IPM on the host for a device-resident LP: A copied to the
+    host in FP64 (the stored values widened; the copy is not timed), then the oracle's iterations
+    from its start point until budget_s has passed (at least one)."""
+    import torch
+    from oracle import ipm as oipm
+    hi = host_info()
+    A = lp.A64[:, :lp.n].cpu().numpy() if lp.A64 is not None else lp.A[:, :lp.n].to(torch.float64).cpu().numpy()
+    b, c = lp.b.cpu().numpy(), lp.c.cpu().numpy()
+    st = oipm.initial_state(A, b, c)
+    prm = oipm.Params()
+    it = 0
+    t0 = time.perf_counter()
+    while it == 0 or time.perf_counter() - t0 < budget_s:
+        new, info = oipm.step(A, b, c, st, prm, "exact")
+        if info.status != oipm.OK:
+            break
+        st = new
+        it += 1
+        log(f"  oracle iteration {it}: {time.perf_counter() - t0:.1f} s")
+    el = time.perf_counter() - t0
+    del A
+    return _baseline_record(it, el, hi, f"first {it} iteration(s) of the same {lp.m}x{lp.n} LP with the oracle's "
+                                        f"direct-solver (dense Cholesky of A D^2 A^T, 8e12 flop per iteration) FP64 "
+                                        f"IPM, A widened to FP64 on the host, {el:.1f} s wall")
+
+
+def host_certificate(lp, state, block: int = 1 << 17) -> dict:
+    """The stop test of a device LP's final point recomputed on the host in FP64 from the stored
+    A (streamed in column blocks): relative gap and residuals. With x > 0, s > 0 and residuals at
+    rounding level, the objective c^T x is an upper bound of the optimum within the gap."""
+    import torch
+    x, y, s = (t.cpu().numpy() for t in (state.x, state.y, state.s))
+    b, c = lp.b.cpu().numpy(), lp.c.cpu().numpy()
+    Ax = np.zeros(lp.m)
+    rd2 = 0.0
+    for j0 in range(0, lp.n, block):
+        j1 = min(lp.n, j0 + block)
+        Ab = lp.A[:, j0:j1].to(torch.float64).cpu().numpy()
+        Ax += Ab @ x[j0:j1]
+        r = Ab.T @ y + s[j0:j1] - c[j0:j1]
+        rd2 += float(r @ r)
+    obj, dual = float(c @ x), float(b @ y)
+    return {"objective": obj, "relgap": abs(obj - dual) / (1 + abs(obj)),
+            "rp_rel": float(np.linalg.norm(Ax - b) / (1 + np.linalg.norm(b))),
+            "rd_rel": float(np.sqrt(rd2) / (1 + np.linalg.norm(c))),
+            "positive": bool(np.all(x > 0) and np.all(s > 0))}
 
 
 def timed_solve(P, ctx, prob, prm, net=None, timing=False, start=None):
     """One full solve from x = s = 1, y = 0 (or from ``start()``, a fresh State), wall-clocked
-    between device synchronizations."""
+    between device synchronizations; with ``timing`` the measured kernels carry HIP events on
+    every TIMING_PERIOD-th launch. The result object is under "_res" (dropped before output)."""
     import torch
     st = start() if start is not None else None
     torch.cuda.synchronize()
     if timing:
-        ctx.set_timing(True)
+        ctx.set_timing(TIMING_PERIOD)
     t0 = time.perf_counter()
     res = P.solve(ctx, prob, prm, net=net, st=st)
     torch.cuda.synchronize()
@@ -118,7 +206,7 @@ def timed_solve(P, ctx, prob, prm, net=None, timing=False, start=None):
         ctx.set_timing(False)
     last = res.infos[-1]
     steps = [i for i in res.infos if i["rc"] != P.IPM_CONVERGED]
-    return {
+    return {"_res": res,
         "converged": bool(res.converged), "iterations": res.iterations, "seconds": el,
         "iter_per_s": res.iterations / el if el > 0 else None,
         "cg_iterations": int(sum(i["pcg_iters"] for i in steps)),
@@ -149,6 +237,7 @@ def algorithm2_comparison(P, ctx, lp, prob, w, s):
         timed_solve(P, ctx, prob, prm, start=start)
         out[name] = timed_solve(P, ctx, prob, prm, start=start)
         out[name].pop("kernels", None)
+        out[name].pop("_res", None)
         log(f"  {name}: {out[name]['iterations']} iterations, {out[name]['iter_per_s']:.1f} it/s")
     return out
 
@@ -213,32 +302,39 @@ def solver_comparison(P, ctx, prob, w, s):
     return out
 
 
-def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
-    """Plain FP64 form vs the mixed-precision form with the learned warm start on one held-out LP
-    of an LP family, both solved to the same stop test; the network is trained first (untimed)
-    on plain-form trajectories of the family's training seeds."""
+FORM_KEYS = ("converged", "iterations", "seconds", "iter_per_s", "cg_iterations", "max_cg_iterations",
+             "refine_rounds", "warm_kept", "final_relgap", "final_rp_rel", "final_rd_rel", "objective")
+
+
+def forms_comparison(P, ctx, family: str, train_seeds: int, epochs: int, test_lp=None, plain=None):
+    """The plain FP64 form against the mixed-precision forms (low-precision storage of the same
+    values) with zero, previous-dy and learned warm starts on one held-out LP of a family, every
+    form solved to the same stop test, one whole solve each (HIP events on every TIMING_PERIOD-th
+    launch of the measured kernels). The network is trained first (untimed) on plain-form
+    trajectories of the family's training seeds. Every form's final point is certified on the
+    host in FP64 (host_certificate). ``test_lp`` / ``plain``: the held-out LP and its plain-form
+    record when the caller already has them."""
     import torch
     from lpgen import device as gdev
     from paper_2209_08722_amd import learned as L
-    if which == "illcond_2000x200000":
-        m, n, w, s, storage = 2000, 200_000, 8000, 2, "f32"
-        make = lambda sd: gdev.illcond_lp(m, n, seed=sd, storage=storage)
+    if family == "illcond_2000x200000":
+        m, n, w, s, storage, test_seed = 2000, 200_000, 8000, 2, "f32", 64
+        make = lambda sd: gdev.illcond_lp(m, n, seed=sd, storage=storage)  # noqa: E731
         desc = ("ill-conditioned A = U diag(sigma) V^T, 2000x200000, sigma log-spaced 1..1e4, FP32 storage "
                 "(FP64 copy for the plain form), w=8000 s=2")
-        test_seed = 64
     else:
-        m, n, w, s, storage = 2000, 2_000_000, 16000, 2, "bf16"
-        make = lambda sd: gdev.dense_lp(m, n, seed=sd, storage=storage, matrix_seed=0)
+        m, n, w, s, storage, test_seed = 2000, 2_000_000, 16000, 2, "bf16", 64
+        if test_lp is None:
+            test_lp = gdev.dense_lp(m, n, seed=test_seed, storage=storage, matrix_seed=0)
+        base = test_lp
+        make = lambda sd: gdev.with_seed(base, sd)  # noqa: E731
         desc = ("dense 2000x2000000 A iid N(0,1) (one A, (b, c) per seed), BF16 storage (FP64 copy for the "
                 "plain form), w=16000 s=2")
-        test_seed = 64
     prm_plain = P.Params(w=w, s=s, seed=0)
     prm_mixed = P.Params(w=w, s=s, seed=0, precision=P.IPM_MIXED)
 
     def problems(lp):
-        low = P.Problem(P.Matrix(lp.A, lp.n), lp.b, lp.c)
-        wide = P.Problem(P.Matrix(lp.A64, lp.n), lp.b, lp.c)
-        return low, wide
+        return P.Problem(P.Matrix(lp.A, lp.n), lp.b, lp.c), P.Problem(P.Matrix(lp.A64, lp.n), lp.b, lp.c)
 
     log(f"forms: training the warm-start network on {train_seeds} plain-form solves ({desc})")
     t0 = time.perf_counter()
@@ -258,44 +354,47 @@ def forms_comparison(P, ctx, which: str, train_seeds: int, epochs: int):
     t_train = time.perf_counter() - t0
     log(f"forms: {X.shape[0]} samples, loss {l0:.3f} -> {hist[-1]:.3f} in {t_train:.1f} s")
 
-    lp = make(test_seed)
+    lp = test_lp if test_lp is not None else make(test_seed)
     low, wide = problems(lp)
     out = {"workload": desc, "m": m, "n": n, "w": w, "s": s, "test_seed": test_seed,
            "training": {"seeds": train_seeds, "samples": int(X.shape[0]), "epochs": epochs,
                         "loss_first": l0, "loss_last": hist[-1], "seconds": t_train}}
     runs = [("plain_fp64", wide, prm_plain, None), ("mixed", low, prm_mixed, None),
             ("mixed_prev", low, P.Params(w=w, s=s, seed=0, precision=P.IPM_MIXED, warm_start=P.IPM_WARM_PREV), None),
-            ("mixed_learned", low, prm_mixed, net)]
-    if which == "3":
-        runs.append(("mixed_f32acc", low, P.Params(w=w, s=s, seed=0, precision=P.IPM_MIXED_F32ACC), None))
-    warmed = set()
+            ("mixed_learned", low, prm_mixed, net),
+            ("mixed_f32acc", low, P.Params(w=w, s=s, seed=0, precision=P.IPM_MIXED_F32ACC), None)]
+    warmed = {P.IPM_PLAIN} if train_seeds > 0 else set()
     for name, prob, prm, nt in runs:
-        # one untimed solve per precision first (workspaces, code paths); the plain form is
-        # already warm from the training solves
-        key = prm.precision
-        if key not in warmed and not (key == P.IPM_PLAIN and train_seeds > 0):
-            timed_solve(P, ctx, prob, prm, net=nt)
-        warmed.add(key)
-        r = timed_solve(P, ctx, prob, prm, net=nt)        # wall clock, no per-kernel events
-        if name in ("plain_fp64", "mixed_learned"):
-            r["kernels"] = timed_solve(P, ctx, prob, prm, net=nt, timing=True)["kernels"]
+        if name == "plain_fp64" and plain is not None:
+            out[name] = plain
+            continue
+        if prm.precision not in warmed:
+            # a few untimed steps per precision first (workspaces, code paths)
+            st = P.State.initial(m, n)
+            for _ in range(3):
+                P.ipm_step(ctx, prob, st, prm)
+            warmed.add(prm.precision)
+        r = timed_solve(P, ctx, prob, prm, net=nt, timing=True)
+        r["host_certificate"] = host_certificate(lp, r.pop("_res").state)
         log(f"forms: {name}: {r['iterations']} iterations in {r['seconds']:.3f} s "
-            f"({r['iter_per_s']:.2f} it/s), CG {r['cg_iterations']}, obj {r['objective']:.12e}")
+            f"({r['iter_per_s']:.2f} it/s), CG {r['cg_iterations']}, obj {r['objective']:.12e}, "
+            f"host relgap {r['host_certificate']['relgap']:.2e}")
         out[name] = r
     ref = out["plain_fp64"]["objective"]
     for name, *_ in runs:
         out[name]["objective_rel_diff_vs_plain"] = abs(out[name]["objective"] - ref) / (1 + abs(ref))
     out["speedup_mixed_learned_vs_plain"] = out["mixed_learned"]["iter_per_s"] / out["plain_fp64"]["iter_per_s"]
     out["time_to_gap_ratio"] = out["plain_fp64"]["seconds"] / out["mixed_learned"]["seconds"]
-    # matvec bandwidth of the low-precision inner matvec (algorithmic bytes: A once + d^2)
-    ms, cnt = out["mixed_learned"]["kernels"]["matvec64"]
     esz = 4 if storage == "f32" else 2
+    ms, cnt = out["mixed_learned"]["kernels"].get("matvec64", (0.0, 0))
     if cnt:
         out["matvec_lowprec_storage_hbm_gbps"] = (m * n * esz + n * 8) / (ms / cnt * 1e-3) / 1e9
-    ms, cnt = out["plain_fp64"]["kernels"]["matvec64"]
+    ms, cnt = out["plain_fp64"]["kernels"].get("matvec64", (0.0, 0))
     if cnt:
         out["matvec_fp64_hbm_gbps"] = (m * n * 8 + n * 8) / (ms / cnt * 1e-3) / 1e9
-    del low, wide, lp
+    del low, wide
+    if test_lp is None:
+        del lp
     torch.cuda.empty_cache()
     return out
 
@@ -416,22 +515,73 @@ def kernel_only(args) -> int:
     return 0
 
 
+def timed_window(P, ctx, prob, prm, m, n, steps: int, warmup: int):
+    """`warmup` untimed steps from a fresh start, then `steps` steps timed from iteration 0 of a
+    fresh solve (the state is reset to the start after each converged solve), bracketed by
+    device synchronizations; HIP events on every TIMING_PERIOD-th launch of the measured kernels."""
+    import torch
+    st = P.State.initial(m, n)
+    conv = []
+
+    def one_step(st):
+        while True:
+            info = P.ipm_step(ctx, prob, st, prm)
+            if info["rc"] == P.IPM_CONVERGED:
+                conv.append((st.k, info))
+                st = P.State.initial(m, n)
+                continue
+            return st, info
+
+    log(f"warmup {warmup} steps")
+    for _ in range(warmup):
+        st, _ = one_step(st)
+    st = P.State.initial(m, n)
+    torch.cuda.synchronize()
+    ctx.set_timing(TIMING_PERIOD)
+    pcg = []
+    log(f"timing {steps} steps from iteration 0 of a fresh solve")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        st, info = one_step(st)
+        pcg.append(info["pcg_iters"])
+        if (i + 1) % 10 == 0:
+            log(f"  step {i + 1}/{steps}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {name: ctx.kernel_time(kid) for name, kid in (("matvec", P.native.IPM_KERNEL_MATVEC),
+                                                     ("sketch", P.native.IPM_KERNEL_SKETCH),
+                                                     ("gram", P.native.IPM_KERNEL_GRAM))}
+    ctx.set_timing(False)
+    return {"seconds": el, "pcg_iters": pcg, "kernels": kt, "last_k": st.k}
+
+
+def roofline_record(kernel_ms, launches, nbytes, probe_gbps, traffic, kernel, probe_desc):
+    avg = kernel_ms / max(launches, 1) * 1e-3
+    gbs = nbytes / avg / 1e9 if launches else None
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (gbs / HBM_PEAK_GBS) if gbs else None, "traffic": traffic, "kernel": kernel,
+            "algorithmic_bytes_per_launch": nbytes, "avg_launch_us": avg * 1e6, "timed_launches": launches,
+            "timing_period": TIMING_PERIOD, "measured_peak": probe_gbps,
+            "frac_measured": (gbs / probe_gbps) if (gbs and probe_gbps) else None,
+            "measured_peak_kernel": probe_desc}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # defaults: one full solve (48 iterations on the 500 x 100000 LP) of warm-up, then two full
-    # solves timed, so the rate is the whole-solve average rather than that of a phase of it
-    ap.add_argument("--steps", type=int, default=96)
-    ap.add_argument("--warmup", type=int, default=48)
-    ap.add_argument("--workload", default="dense_500x100000", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="dense_2000x2000000", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the Algorithm 2 comparison and the v-correction ablation")
-    ap.add_argument("--forms", default="illcond_2000x200000",
-                    choices=["illcond_2000x200000", "dense_2000x2000000", "none"],
-                    help="workload of the plain vs mixed+learned comparison")
-    ap.add_argument("--train-seeds", type=int, default=8)
+    ap.add_argument("--extras", action="store_true",
+                    help="also run the Algorithm 2 comparison, the v-correction ablation, the sketch and inner-solver "
+                         "comparisons (on the workload's LP; host workloads only)")
+    ap.add_argument("--forms", default="auto", choices=["auto", "illcond_2000x200000", "dense_2000x2000000", "none"],
+                    help="family of the plain vs mixed+learned comparison (auto: the 2000x2000000 workload itself "
+                         "when it is the benchmark's, else none)")
+    ap.add_argument("--train-seeds", type=int, default=2)
     ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
@@ -472,76 +622,60 @@ def main() -> int:
     import paper_2209_08722_amd as P
 
     wl = WORKLOADS[args.workload]
+    m, n, w, s = wl["m"], wl["n"], wl["w"], wl["s"]
+    on_device = wl.get("device", False)
     log(f"generating workload {args.workload}: {wl['desc']}")
-    lp = lpgen.workload(args.workload, seed=wl["seed"])
-    m, n, w, s = lp.m, lp.n, wl["w"], wl["s"]
+    if on_device:
+        from lpgen import device as gdev
+        lp = gdev.dense_lp(m, n, seed=wl["seed"], storage=wl["storage"], matrix_seed=0)
+        prob = P.Problem(P.Matrix(lp.A64, n), lp.b, lp.c)
+        esz = 8
+    else:
+        lp = lpgen.workload(args.workload, seed=wl["seed"])
+        prob = P.Problem.from_lp(lp)
+        esz = 8
     ctx = P.Context(0)
-    prob = P.Problem.from_lp(lp)
-    prm = P.Params(w=w, s=s, seed=wl["seed"])
+    prm = P.Params(w=w, s=s, seed=0 if on_device else wl["seed"])
     torch.cuda.synchronize()
 
-    def fresh():
-        return P.State.initial(m, n)
+    win = timed_window(P, ctx, prob, prm, m, n, args.steps, args.warmup)
+    el = win["seconds"]
+    mv_ms, mv_n = win["kernels"]["matvec"]
+    sk_ms, sk_n = win["kernels"]["sketch"]
+    gr_ms, gr_n = win["kernels"]["gram"]
 
-    st = fresh()
-    solves = 0
-    conv_iters = []
-    last = {}
+    # whole solves from the start: the rate over complete solves (iterations to the stop test over
+    # wall time), which the window above only samples
+    log("whole solve (plain FP64)")
+    whole = timed_solve(P, ctx, prob, prm, timing=True)
+    res = whole.pop("_res")
+    if on_device:
+        whole["host_certificate"] = host_certificate(lp, res.state)
+    else:
+        x, y, s_ = (t.cpu().numpy() for t in (res.state.x, res.state.y, res.state.s))
+        obj = float(lp.c @ x)
+        whole["host_certificate"] = {
+            "objective": obj, "relgap": abs(obj - float(lp.b @ y)) / (1 + abs(obj)),
+            "rp_rel": float(np.linalg.norm(lp.A @ x - lp.b) / (1 + np.linalg.norm(lp.b))),
+            "rd_rel": float(np.linalg.norm(lp.A.T @ y + s_ - lp.c) / (1 + np.linalg.norm(lp.c))),
+            "positive": bool(np.all(x > 0) and np.all(s_ > 0))}
+    del res
+    log(f"  {whole['iterations']} iterations in {whole['seconds']:.2f} s = {whole['iter_per_s']:.2f} it/s, "
+        f"CG {whole['cg_iterations']}, host relgap {whole['host_certificate']['relgap']:.2e}")
 
-    def one_step():
-        nonlocal st, solves, last
-        while True:
-            info = P.ipm_step(ctx, prob, st, prm)
-            if info["rc"] == P.IPM_CONVERGED:
-                solves += 1
-                conv_iters.append(st.k)
-                last = info
-                st = fresh()
-                continue
-            return info
-
-    log(f"warmup {args.warmup} steps")
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    ctx.set_timing(TIMING_PERIOD)
-    pcg_iters = []
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        info = one_step()
-        pcg_iters.append(info["pcg_iters"])
-        if (i + 1) % 24 == 0:
-            log(f"  step {i + 1}/{args.steps}")
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    mv_ms, mv_n = ctx.kernel_time(P.native.IPM_KERNEL_MATVEC)
-    gpu_seconds = el
-    sk_ms, sk_n = ctx.kernel_time(P.native.IPM_KERNEL_SKETCH)
-    gr_ms, gr_n = ctx.kernel_time(P.native.IPM_KERNEL_GRAM)
-    ctx.set_timing(False)
-
-    # finish the current solve (untimed) to report the accuracy reached
-    while True:
-        info = P.ipm_step(ctx, prob, st, prm)
-        if info["rc"] == P.IPM_CONVERGED:
-            conv_iters.append(st.k)
-            last = info
-            break
-
-    esz = 8
     a_bytes = m * n * esz
     mv_bytes = a_bytes + n * 8                     # A once + d^2 (algorithmic, per launch)
-    log("stream probe at the matvec's bytes")
-    probe = stream_probe(P, ctx, mv_bytes)
+    probe_bytes = min(mv_bytes, 8 * 10**9)
+    log(f"stream probe over {probe_bytes / 1e9:.2f} GB")
+    probe = stream_probe(P, ctx, probe_bytes)
     sk_bytes = a_bytes + n * 8 + m * w * 8         # A once + d + B written
     gram_flops = float(m) * m * w                  # SYRK count m^2 w
-    mv_avg = mv_ms / max(mv_n, 1) * 1e-3
-    mv_gbs = mv_bytes / mv_avg / 1e9 if mv_n else None
     sk_gbs = sk_bytes / (sk_ms / max(sk_n, 1) * 1e-3) / 1e9 if sk_n else None
     gr_tf = gram_flops / (gr_ms / max(gr_n, 1) * 1e-3) / 1e12 if gr_n else None
-    traffic = traffic_record(args.workload)
+    probe_desc = (f"ipm_stream_read: read-only pass over {probe_bytes / 1e9:.2f} GB, the same access pattern "
+                  f"(k_stream_read)")
+    roof = roofline_record(mv_ms, mv_n, mv_bytes, probe["read_gbps"], traffic_record(args.workload),
+                           "CG matvec pass q = A D^2 A^T v, FP64 storage (k_strip OpMatvec)", probe_desc)
 
     out = {
         "metric": "IPM iter/s + matvec HBM GB/s, FP64 plain vs mixed+learned at gap 1e-8",
@@ -556,27 +690,18 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl["desc"], "m": m, "n": n, "w": w, "s": s, "form": "plain FP64",
-                   "iters_to_gap": conv_iters[-1] if conv_iters else None,
-                   "final_relgap": last.get("relgap"), "final_rp_rel": last.get("rp_rel"),
-                   "final_rd_rel": last.get("rd_rel"), "mean_pcg_iters": float(np.mean(pcg_iters)),
-                   "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (mv_gbs / HBM_PEAK_GBS) if mv_gbs else None, "traffic": traffic,
-                     "kernel": "CG matvec pass q = A D^2 A^T v (k_strip OpMatvec)",
-                     "algorithmic_bytes_per_launch": mv_bytes, "avg_launch_us": mv_avg * 1e6,
-                     "timed_launches": mv_n, "timing_period": TIMING_PERIOD,
-                     "measured_peak": probe["read_gbps"],
-                     "frac_measured": (mv_gbs / probe["read_gbps"]) if mv_gbs else None,
-                     "measured_peak_kernel": "ipm_stream_read: read-only pass over the same bytes, same access "
-                                             "pattern (k_stream_read)"},
+        "config": {"workload": args.workload, "description": wl["desc"], "m": m, "n": n, "w": w, "s": s,
+                   "form": "plain FP64", "window": f"IPM iterations 0-{args.steps - 1} of a fresh solve",
+                   "mean_pcg_iters_window": float(np.mean(win["pcg_iters"])), "parallelism": "1 GPU"},
+        "whole_solve": {**whole, "note": "one complete solve from the start; the rate to quote"},
+        "roofline": roof,
         "stream_probe": probe,
-        "matvec_hbm_gbps": mv_gbs,
+        "matvec_hbm_gbps": roof["achieved"],
         "sketch_hbm_gbps": sk_gbs,
         "gram_tflops": gr_tf,
         "gram_mfma_frac": (gr_tf / FP64_MFMA_PEAK_TFLOPS) if gr_tf else None,
     }
-    if not args.no_extras:
+    if args.extras and not on_device:
         log("feasible (Algorithm 2) vs infeasible (Algorithm 3) IPM")
         out["algorithms"] = algorithm2_comparison(P, ctx, lp, prob, w, s)
         log("v-correction ablation on l1-SVM LPs")
@@ -585,13 +710,37 @@ def main() -> int:
         out["sketches"] = sketch_comparison(P, ctx, prob, m, n, w, s)
         log("CG vs Chebyshev inner solver")
         out["inner_solvers"] = solver_comparison(P, ctx, prob, w, s)
-    if args.forms != "none":
-        out["forms"] = forms_comparison(P, ctx, args.forms, args.train_seeds, args.epochs)
+    forms = args.forms
+    if forms == "auto":
+        forms = "dense_2000x2000000" if args.workload == "dense_2000x2000000" else "none"
+    if forms != "none":
+        same = forms == args.workload
+        out["forms"] = forms_comparison(P, ctx, forms, args.train_seeds, args.epochs,
+                                        test_lp=lp if same else None,
+                                        plain={k: v for k, v in whole.items()} if same else None)
+        f = out["forms"]
+        ms, cnt = f["mixed_learned"]["kernels"].get("matvec64", (0.0, 0))
+        esz_low = 2 if forms == "dense_2000x2000000" else 4
+        if cnt:
+            out["roofline_mixed_matvec"] = roofline_record(
+                ms, cnt, f["m"] * f["n"] * esz_low + f["n"] * 8, probe["read_gbps"], None,
+                f"CG matvec pass of the mixed form, {'BF16' if esz_low == 2 else 'FP32'} storage, FP64 "
+                f"accumulation (k_strip OpMatvec)", probe_desc)
+        out["headline_comparison"] = {
+            "plain_fp64_iter_per_s": f["plain_fp64"]["iter_per_s"],
+            "mixed_learned_iter_per_s": f["mixed_learned"]["iter_per_s"],
+            "ratio": f["speedup_mixed_learned_vs_plain"],
+            "objective_rel_diff": f["mixed_learned"]["objective_rel_diff_vs_plain"],
+            "host_relgap_plain": f["plain_fp64"]["host_certificate"]["relgap"],
+            "host_relgap_mixed_learned": f["mixed_learned"]["host_certificate"]["relgap"],
+            "note": "whole solves of the same LP; each objective is an upper bound of the optimum within its "
+                    "host-recomputed FP64 relative gap (x, s > 0, residuals at rounding level)"}
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle) for ~{args.cpu_budget:.0f} s")
-        out["cpu_baseline"] = cpu_baseline(lp, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline_device_lp(lp, args.cpu_budget) if on_device \
+            else cpu_baseline(lp, args.cpu_budget)
     ctx.close()
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=float), flush=True)
     return 0
 
 

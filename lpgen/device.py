@@ -59,6 +59,18 @@ def _finish(A_vals, storage, seed, device, widen, name):
     del A_vals
     A64 = _padded(m, n, torch.float64, device)
     A64[:, :n] = A[:, :n].to(torch.float64)
+    b, c, x0, y0, s0 = _rhs(A64, n, seed, device)
+    lp = DeviceLP(A, n, b, c, x0, y0, s0, storage, A64 if widen else None, name)
+    if not widen:
+        del A64
+    return lp
+
+
+def _rhs(A64, n, seed, device):
+    """The witness pair x0 ~ U(0.5, 1.5)^n, y0 ~ N(0, 1)^m, s0 ~ U(0.5, 1.5)^n (generator seeded
+    by seed + 7919) and b = A x0, c = A^T y0 + s0 in FP64."""
+    torch = _torch()
+    m = A64.shape[0]
     g = torch.Generator(device=device)
     g.manual_seed(seed + 7919)
     x0 = torch.rand(n, generator=g, dtype=torch.float64, device=device) + 0.5
@@ -66,10 +78,17 @@ def _finish(A_vals, storage, seed, device, widen, name):
     s0 = torch.rand(n, generator=g, dtype=torch.float64, device=device) + 0.5
     b = A64[:, :n] @ x0
     c = A64[:, :n].T @ y0 + s0
-    lp = DeviceLP(A, n, b, c, x0, y0, s0, storage, A64 if widen else None, name)
-    if not widen:
-        del A64
-    return lp
+    return b, c, x0, y0, s0
+
+
+def with_seed(lp: DeviceLP, seed: int) -> DeviceLP:
+    """The LP of the same family with (b, c) from ``seed``: the same A (and FP64 copy, which must
+    be present), a new witness pair. Equal to building the family member at ``seed`` with the
+    same matrix seed, without drawing A again."""
+    if lp.A64 is None:
+        raise ValueError("with_seed needs the FP64 copy of A")
+    b, c, x0, y0, s0 = _rhs(lp.A64, lp.n, seed, lp.A.device)
+    return DeviceLP(lp.A, lp.n, b, c, x0, y0, s0, lp.storage, lp.A64, f"{lp.name}_rhs{seed}")
 
 
 def dense_lp(m: int, n: int, seed: int = 0, storage: str = "bf16", device: str = "cuda:0",

@@ -94,6 +94,58 @@ __device__ __forceinline__ V sum8_lanes(V v) {
     return v;
 }
 
+// Eight sums over each group of eight consecutive lanes at once, scattered: lane c of the group
+// returns the group's sum of v[c]. A reduce-scatter: the half-row mirror pairs lane c with 7-c
+// (different halves of the index range), then quad xor 2 and quad xor 1; each stage sends the
+// half of the values the partner keeps. 7 DPP moves and 7 adds, against 24 of each for eight
+// separate group sums. All 64 lanes must be active.
+// First stage alone, for values j and j + 4 (so a caller can produce the eight values in pairs
+// and keep four partial sums live instead of eight values): lane c keeps value j + 4 (c & 4) summed
+// with lane 7 - c's.
+template <typename V>
+__device__ __forceinline__ V reduce_scatter8_first(V lo, V hi, int c) {
+    const bool b2 = (c & 4) != 0;
+    return (b2 ? hi : lo) + dpp_mov<kDppHalfMirror>(b2 ? lo : hi);
+}
+
+// The remaining two stages on the four partial sums of reduce_scatter8_first.
+template <typename V>
+__device__ __forceinline__ V reduce_scatter8_rest(const V (&k4)[4], int c) {
+    const bool b1 = (c & 2) != 0, b0 = (c & 1) != 0;
+    V k2[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const V send = b1 ? k4[j] : k4[j + 2];
+        const V keep = b1 ? k4[j + 2] : k4[j];
+        k2[j] = keep + dpp_mov<kDppQuadXor2>(send);
+    }
+    const V send = b0 ? k2[0] : k2[1];
+    const V keep = b0 ? k2[1] : k2[0];
+    return keep + dpp_mov<kDppQuadXor1>(send);
+}
+
+template <typename V>
+__device__ __forceinline__ V reduce_scatter8(const V (&v)[8], int c) {
+    const bool b2 = (c & 4) != 0, b1 = (c & 2) != 0, b0 = (c & 1) != 0;
+    V k4[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const V send = b2 ? v[j] : v[j + 4];
+        const V keep = b2 ? v[j + 4] : v[j];
+        k4[j] = keep + dpp_mov<kDppHalfMirror>(send);
+    }
+    V k2[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const V send = b1 ? k4[j] : k4[j + 2];
+        const V keep = b1 ? k4[j + 2] : k4[j];
+        k2[j] = keep + dpp_mov<kDppQuadXor2>(send);
+    }
+    const V send = b0 ? k2[0] : k2[1];
+    const V keep = b0 ? k2[1] : k2[0];
+    return keep + dpp_mov<kDppQuadXor1>(send);
+}
+
 // Sum over each group of W consecutive lanes (W = 1, 2, 4, 8, 16, 32 or 64).
 template <int W, typename V>
 __device__ __forceinline__ V group_sum(V v) {

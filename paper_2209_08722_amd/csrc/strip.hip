@@ -11,8 +11,8 @@
 //     one LDS exchange across waves (double-buffered, one barrier per strip);
 //   - the strip stays in registers as raw 16-byte words, converted to the accumulation type at use;
 //   - row sums: per-thread register accumulators reduced over the column lanes once at the end
-//     of the persistent loop, or (more than 16 rows per thread) reduced over the column lanes
-//     every strip and added into an LDS row-sum array;
+//     of the persistent loop, or (more than 16 rows per thread) reduce-scattered over the eight
+//     column lanes every strip (lane c keeps every eighth row's running sum in registers);
 //   - each block writes its partial row sums as part[acc][row][block]; a second kernel reduces
 //     them with one wave per row (coalesced over blocks) in a fixed order and applies the
 //     post-processing step (r_p, p, the true residual, ...).
@@ -120,7 +120,14 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     ACC* vs = reinterpret_cast<ACC*>(smem_raw);   // [MPAD]        vector dotted with columns
     ACC* red = vs + MPAD;                            // [2][NW][SW]   per-wave column dots
-    double* qs = reinterpret_cast<double*>(red + 2 * NW * SW);   // [NA][MPAD] row sums (QL only)
+    // QL row sums [NA][RPT][RG + 8]: row g + RG k at k (RG + 8) + g; the padding puts the eight
+    // rows a wave's lane c of eight row groups add at once into distinct bank pairs but for c
+    // and c + 4
+    constexpr int QS_K = RG + 8, QS_A = RPT * QS_K;
+    // FP32 storage with FP64 accumulation (four conversions per word) has no registers left for
+    // the reduce-scatter's partial sums at 32 rows per thread; it sums each row on its own
+    constexpr bool RS = !(sizeof(T) == 4 && sizeof(ACC) == 8 && RPT > 24);
+    double* qs = reinterpret_cast<double*>(red + 2 * NW * SW);
     __shared__ double shr[NW];
 
     const int tid = threadIdx.x;
@@ -131,7 +138,7 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
 
     for (int i = tid; i < MPAD; i += NT) vs[i] = (i < m) ? (ACC)a.vec0[i] : (ACC)0;
     if constexpr (QL) {
-        for (int i = tid; i < NA * MPAD; i += NT) qs[i] = 0.0;
+        for (int i = tid; i < NA * QS_A; i += NT) qs[i] = 0.0;
     }
     __syncthreads();
     const typename Op::S st = Op::init(a);
@@ -141,6 +148,11 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     // scalar base and one 32-bit VGPR offset.
     const uint32_t lane_off = (uint32_t)g * (uint32_t)a.ld + (uint32_t)(c * VEC);
 
+    // row sums: with QL, per strip the eight column lanes of a row group reduce-scatter the sums
+    // of eight rows, and lane c adds row g + RG (8 t + c) into the LDS row-sum array qs (one
+    // LDS atomic per lane per eight rows, all lanes of a wave on distinct rows); without QL each
+    // thread keeps its own rows' column-lane partials in q and reduces them at the end
+    static_assert(!QL || RPT % 8 == 0, "QL needs a multiple of 8 rows per thread");
     ACC q[NA][QL ? 1 : RPT];
 #pragma unroll
     for (int aa = 0; aa < NA; ++aa)
@@ -199,29 +211,66 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
         // converting again. The empty asm emits no instruction.
 #pragma unroll
         for (int k = 0; k < RPT; ++k) asm volatile("" : "+v"(av[k].x), "+v"(av[k].y), "+v"(av[k].z), "+v"(av[k].w));
+        if constexpr (QL && !RS) {
+            // one group sum per row, added by the row's first column lane
 #pragma unroll
-        for (int k = 0; k < RPT; ++k)
+            for (int k = 0; k < RPT; ++k)
 #pragma unroll
-            for (int aa = 0; aa < NA; ++aa) {
-                ACC sacc = (ACC)0;
+                for (int aa = 0; aa < NA; ++aa) {
+                    ACC sacc = (ACC)0;
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) sacc += Elem<T>::template get<ACC>(av[k], e) * coef[aa][e];
-                if constexpr (QL) {
-                    // sum over the LPR column lanes of this row, then one lane updates the LDS row sum
+                    for (int e = 0; e < VEC; ++e) sacc += Elem<T>::template get<ACC>(av[k], e) * coef[aa][e];
                     sacc = group_sum<LPR>(sacc);
-                    if (c == 0) qs[aa * MPAD + g + RG * k] += (double)sacc;
-                } else {
+                    if (c == 0) atomicAdd(&qs[aa * QS_A + k * QS_K + g], (double)sacc);
+                }
+        } else if constexpr (QL) {
+#pragma unroll
+            for (int t = 0; t < RPT / 8; ++t) {
+                // rows 8t + j and 8t + j + 4 together, straight into the first stage
+                ACC k4[NA][4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    ACC lo[NA], hi[NA];
+#pragma unroll
+                    for (int aa = 0; aa < NA; ++aa) lo[aa] = hi[aa] = (ACC)0;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const ACC xl = Elem<T>::template get<ACC>(av[8 * t + j], e);
+                        const ACC xh = Elem<T>::template get<ACC>(av[8 * t + j + 4], e);
+#pragma unroll
+                        for (int aa = 0; aa < NA; ++aa) {
+                            lo[aa] += xl * coef[aa][e];
+                            hi[aa] += xh * coef[aa][e];
+                        }
+                    }
+#pragma unroll
+                    for (int aa = 0; aa < NA; ++aa) k4[aa][j] = reduce_scatter8_first(lo[aa], hi[aa], c);
+                }
+#pragma unroll
+                for (int aa = 0; aa < NA; ++aa)
+                    atomicAdd(&qs[aa * QS_A + (8 * t + c) * QS_K + g], (double)reduce_scatter8_rest(k4[aa], c));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RPT; ++k)
+#pragma unroll
+                for (int aa = 0; aa < NA; ++aa) {
+                    ACC sacc = (ACC)0;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) sacc += Elem<T>::template get<ACC>(av[k], e) * coef[aa][e];
                     q[aa][k] += sacc;
                 }
-            }
+        }
         buf ^= 1;
     }
 
     if constexpr (QL) {
+        static_assert(LPR == 8, "QL reduce-scatters over eight column lanes");
         __syncthreads();
         for (int i = tid; i < m; i += NT)
 #pragma unroll
-            for (int aa = 0; aa < NA; ++aa) a.part[((int64_t)aa * m + i) * G + blockIdx.x] = qs[aa * MPAD + i];
+            for (int aa = 0; aa < NA; ++aa)
+                a.part[((int64_t)aa * m + i) * G + blockIdx.x] = qs[aa * QS_A + (i / RG) * QS_K + i % RG];
     } else {
         // row sums over the LPR column lanes of each row group
 #pragma unroll
@@ -466,7 +515,7 @@ StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind) {
     const int nw = p.nt / 64;
     const size_t acc = 8;   // sized for FP64 accumulation (enough for FP32 too)
     p.lds = acc * ((size_t)rg * p.rpt + 2 * (size_t)nw * p.sw);
-    if (p.rpt > 16) p.lds += 8 * 2 * (size_t)rg * p.rpt;   // LDS row sums (up to 2 accumulators)
+    if (p.rpt > 16) p.lds += 8 * 2 * (size_t)p.rpt * (rg + 8);   // QL row sums (up to 2 accumulators)
     return p;
 }
 
