@@ -72,9 +72,11 @@ typedef struct ipm_ctx ipm_ctx;
  * Sizes: 1 <= m <= n and m <= 10236 for every layout (the CG kernels keep two FP64 m-vectors
  *   in one block's 160 KB of LDS). A dense A keeps a column strip of all m rows on chip in its
  *   passes, so m <= 2048 with IPM_F64 or IPM_F32 values and m <= 6400 with IPM_BF16 values, and
- *   a thread addresses the rows of its row group (64 rows) with a 32-bit element offset, so
- *   63*ld + 128/elem_size must stay below 2^32 (ld below about 6.8e7 elements). A CSR A needs
- *   n < 2^31. Larger sizes are IPM_ERR_ARG, reported before any device work. */
+ *   a thread addresses the rows of its row group (up to 64 rows) with a 32-bit element offset, so
+ *   63*ld + 128/elem_size must stay below 2^32 (ld below about 6.8e7 elements); for
+ *   1025 <= m <= 2048 the CG matvec reads a 64-row group through one buffer descriptor, so
+ *   64*ld*elem_size must stay below 2^32 (ld below 8.3e6 FP64, 1.6e7 FP32, 3.3e7 BF16 elements). A CSR A needs n < 2^31. Larger sizes are IPM_ERR_ARG, reported before any device
+ *   work. */
 typedef struct {
     int64_t m, n, ld;
     int32_t layout;          /* IPM_DENSE_ROWMAJOR | IPM_CSR */

@@ -223,12 +223,15 @@ int check_matrix(ipm_ctx* ctx, const ipm_matrix* A) {
     if (pl.nt <= 0)
         return fail(ctx, IPM_ERR_ARG, "m=%lld exceeds the dense passes' limit (%d rows with %s values)",
                     (long long)A->m, A->dtype == IPM_BF16 ? 6400 : 2048, A->dtype == IPM_BF16 ? "BF16" : "FP64/FP32");
-    // the strip passes address a thread's rows inside a row group with a 32-bit element offset
+    // the strip passes address a thread's rows inside a row group with a 32-bit element offset;
+    // with more than 16 rows per thread the CG matvec reads a row group through a buffer
+    // descriptor, so the group's bytes must fit 32 bits
     const int64_t rg = pl.nt / pl.lpr;
-    if ((rg - 1) * A->ld + pl.sw > (int64_t)UINT32_MAX)
+    const int64_t lim = (!pl.rr && pl.rpt > 16) ? ((int64_t)UINT32_MAX / es) / rg
+                                                 : ((int64_t)UINT32_MAX - pl.sw) / (rg > 1 ? rg - 1 : 1);
+    if (A->ld > lim)
         return fail(ctx, IPM_ERR_ARG, "ld=%lld too large for the dense passes (at most %lld elements per row at m=%lld)",
-                    (long long)A->ld, (long long)(((int64_t)UINT32_MAX - pl.sw) / (rg > 1 ? rg - 1 : 1)),
-                    (long long)A->m);
+                    (long long)A->ld, (long long)lim, (long long)A->m);
     return IPM_OK;
 }
 

@@ -57,6 +57,17 @@ __device__ __forceinline__ void load_segment(const T* seg, const T* seg0, int64_
     }
 }
 
+// 16 bytes at byte offset voff of one row group of a strip: base is the group's row-0 segment
+// (block-uniform) and nrec the bytes of the group's rows that lie inside A. A buffer load returns
+// zero at offsets >= nrec, so rows past m read as zero with neither a branch nor a mask (both of
+// which made the compiler wait on each load as it was issued). Non-temporal.
+__device__ __forceinline__ uint4 load_group_row(const void* base, uint32_t nrec, uint32_t voff) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                                                       (int)nrec, 0x00020000);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 2);
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
 constexpr int RNT = 256;
 __global__ __launch_bounds__(RNT) void k_rowsum(StripCall a, int G, int nacc, int ncr) {
     if (a.done != nullptr && *a.done) return;
@@ -160,16 +171,49 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
         for (int k = 0; k < (QL ? 1 : RPT); ++k) q[aa][k] = (ACC)0;
     double cr[NCR > 0 ? NCR : 1] = {0.0};
 
+    // ROLL (the CG matvec with many rows per thread, one block per CU, so no other block's loads
+    // cover this one's compute phases): the next strip's rows are loaded into the registers of
+    // this strip's rows as soon as the accumulation phase has used them, so the next strip
+    // streams in during this strip's accumulation and the next strip's column dots. Whole strips
+    // are read with buffer loads (load_group_row); the host keeps each row group's byte offsets
+    // below 2^32.
+    constexpr bool ROLL = QL && RS && Op::PF;
+    const int64_t rowstride = (int64_t)RG * a.ld;
+    const uint32_t lane_bytes = lane_off * (uint32_t)sizeof(T);
+    const uint32_t group_bytes = (uint32_t)((int64_t)RG * a.ld * (int64_t)sizeof(T));
+    // bytes of row group k's rows inside A: all RG rows, fewer for the last group, none past it
+    auto group_nrec = [&](int k) -> uint32_t {
+        const int rows = m - RG * k;
+        return rows >= RG ? group_bytes : (rows > 0 ? (uint32_t)((int64_t)rows * a.ld * (int64_t)sizeof(T)) : 0u);
+    };
+    auto whole = [&](int sidx) { return (int64_t)(sidx + 1) * SW <= a.n; };
     int buf = 0;
-    for (int strip = blockIdx.x; strip < nstrips; strip += G) {
+    double pfv[VEC];
+    uint4 av[RPT];
+    if constexpr (ROLL) {
+        const int strip = blockIdx.x;
         const int64_t j0 = (int64_t)strip * SW + c * VEC;
-        const int64_t left = a.n - j0;
-        double pfv[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) pfv[e] = Op::PF ? Op::pre(a, j0 + e, j0 + e < a.n) : 0.0;
-        uint4 av[RPT];
-        load_segment<T, RPT, true>(A + (int64_t)strip * SW + lane_off, A + (int64_t)strip * SW + c * VEC,
-                                   (int64_t)RG * a.ld, g, RG, m, left, av);
+        if (strip < nstrips) {
+            if (whole(strip)) {
+#pragma unroll
+                for (int k = 0; k < RPT; ++k)
+                    av[k] = load_group_row(A + (int64_t)strip * SW + (int64_t)k * rowstride, group_nrec(k), lane_bytes);
+            } else {
+                load_segment<T, RPT, true>(A + (int64_t)strip * SW + lane_off, A + (int64_t)strip * SW + c * VEC,
+                                           rowstride, g, RG, m, a.n - j0, av);
+            }
+        }
+    }
+    for (int strip = blockIdx.x; strip < nstrips; strip += G) {
+        const int64_t j0 = (int64_t)strip * SW + c * VEC;
+        if constexpr (!ROLL) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) pfv[e] = Op::PF ? Op::pre(a, j0 + e, j0 + e < a.n) : 0.0;
+            load_segment<T, RPT, true>(A + (int64_t)strip * SW + lane_off, A + (int64_t)strip * SW + c * VEC,
+                                       rowstride, g, RG, m, a.n - j0, av);
+        }
         // column dots over this thread's rows
         ACC pd[VEC];
 #pragma unroll
@@ -224,6 +268,13 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
                     if (c == 0) atomicAdd(&qs[aa * QS_A + k * QS_K + g], (double)sacc);
                 }
         } else if constexpr (QL) {
+            const int nxt = strip + G;
+            const int64_t jn = (int64_t)nxt * SW + c * VEC;
+            // the next strip's rows stream in during this accumulation when it is a whole strip
+            // (block-uniform); otherwise strip 0 (whole: these instances need n >= m > 1024) is
+            // read and dropped, and a last, partial strip is read after the accumulation
+            const bool roll_rows = ROLL && nxt < nstrips && whole(nxt);
+            const T* nbase = A + (int64_t)(roll_rows ? nxt : 0) * SW;
 #pragma unroll
             for (int t = 0; t < RPT / 8; ++t) {
                 // rows 8t + j and 8t + j + 4 together, straight into the first stage
@@ -249,6 +300,24 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
 #pragma unroll
                 for (int aa = 0; aa < NA; ++aa)
                     atomicAdd(&qs[aa * QS_A + (8 * t + c) * QS_K + g], (double)reduce_scatter8_rest(k4[aa], c));
+                if constexpr (ROLL) {
+                    // this group of rows is used: its registers take the next strip's rows
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) {
+                        const int k = 8 * t + r;
+                        av[k] = load_group_row(nbase + (int64_t)k * rowstride, group_nrec(k), lane_bytes);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            if constexpr (ROLL) {
+                if (nxt < nstrips) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) pfv[e] = Op::PF ? Op::pre(a, jn + e, jn + e < a.n) : 0.0;
+                    if (!roll_rows)
+                        load_segment<T, RPT, true>(A + (int64_t)nxt * SW + lane_off, A + (int64_t)nxt * SW + c * VEC,
+                                                   rowstride, g, RG, m, a.n - jn, av);
+                }
             }
         } else {
 #pragma unroll

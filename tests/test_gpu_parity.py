@@ -467,6 +467,12 @@ def test_dense_ld_limit_rejected_before_device_work(ctx):
     Ac = P.native.IpmMatrix(m, ld, ld, 0, 0, buf.data_ptr())
     rc = ctx.lib.ipm_normal_matvec(ctx.h, ctypes.byref(Ac), buf.data_ptr(), d2.data_ptr(), d2.data_ptr())
     assert rc == -1 and "ld=" in ctx.lib.ipm_last_error(ctx.h).decode()
+    # 1025 <= m <= 2048: a 64-row group's bytes must fit the 32-bit range of a buffer descriptor
+    m = 1500
+    ld = 1 << 23                                 # 64 * ld * 8 bytes = 2^32
+    Ac = P.native.IpmMatrix(m, ld, ld, 0, 0, buf.data_ptr())
+    rc = ctx.lib.ipm_normal_matvec(ctx.h, ctypes.byref(Ac), buf.data_ptr(), d2.data_ptr(), d2.data_ptr())
+    assert rc == -1 and "ld=" in ctx.lib.ipm_last_error(ctx.h).decode()
 
 
 def test_row_limit_of_the_cg_kernels(ctx):
