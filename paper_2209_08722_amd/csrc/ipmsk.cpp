@@ -1256,18 +1256,21 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
     // in FP32; the Gaussian sketch (an MFMA product) produces B in FP64 in every form.
     const bool gauss = prm->sketch == IPM_SKETCH_GAUSSIAN;
     const int b_f64 = (mixed && !gauss) ? 0 : 1;
-    const int wmax = prm->w << prm->max_redraws;
+    // B is sized for the draw being made: a redraw (w doubled) grows it only when it happens
     void* B = nullptr;
+    auto size_b = [&](int wd) -> int {
+        if (!b_f64) {
+            float* Bf = nullptr;
+            CHK(ws(ctx, W_BF, (size_t)m * (size_t)wd, &Bf));
+            B = Bf;
+        } else {
+            double* Bd = nullptr;
+            CHK(ws(ctx, W_B, (size_t)m * (size_t)wd, &Bd));
+            B = Bd;
+        }
+        return IPM_OK;
+    };
     double *Lw = nullptr, *X = nullptr;
-    if (!b_f64) {
-        float* Bf = nullptr;
-        CHK(ws(ctx, W_BF, (size_t)m * (size_t)wmax, &Bf));
-        B = Bf;
-    } else {
-        double* Bd = nullptr;
-        CHK(ws(ctx, W_B, (size_t)m * (size_t)wmax, &Bd));
-        B = Bd;
-    }
     CHK(ws(ctx, W_L, (size_t)m * m, &Lw));
     CHK(ws(ctx, W_X, (size_t)m * m, &X));
     HashKeys hk{};
@@ -1283,6 +1286,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         const uint64_t seed_a = a == 0 ? prm->seed : prm->seed + (uint64_t)a * 0x632BE59BD9B4E019ull;
         hk = make_keys(seed_a, state->k, w_used, s_used);
         gkey = gauss_key(seed_a, state->k);
+        CHK(size_b(w_used));
         if (gauss) CHK(do_sketch_gauss(ctx, A, d2, 1, gkey, w_used, reinterpret_cast<double*>(B)));
         else CHK(do_sketch(ctx, A, d2, 1, hk, w_used, b_f64, B));
         int64_t bad = -1;
@@ -1337,7 +1341,7 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         CHK(run_pass(ctx, A, c, -1, -1));
     }
     double* u = nullptr;
-    CHK(ws(ctx, W_U, (size_t)wmax, &u));
+    CHK(ws(ctx, W_U, (size_t)w_used, &u));
     if (prm->vcorr) {
         double* XT = nullptr;
         CHK(ws(ctx, W_XT, (size_t)m * m, &XT));   // written by do_pcg for this draw

@@ -136,8 +136,10 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     // and c + 4
     constexpr int QS_K = RG + 8, QS_A = RPT * QS_K;
     // FP32 storage with FP64 accumulation (four conversions per word) has no registers left for
-    // the reduce-scatter's partial sums at 32 rows per thread; it sums each row on its own
-    constexpr bool RS = !(sizeof(T) == 4 && sizeof(ACC) == 8 && RPT > 24);
+    // the reduce-scatter's partial sums at 32 rows per thread in the residual and direction
+    // passes; there it sums each row on its own (the CG matvec, with its buffer-loaded rolling
+    // strip, keeps the reduce-scatter)
+    constexpr bool RS = (QL && Op::PF) || !(sizeof(T) == 4 && sizeof(ACC) == 8 && RPT > 24);
     double* qs = reinterpret_cast<double*>(red + 2 * NW * SW);
     __shared__ double shr[NW];
 
