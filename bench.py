@@ -201,7 +201,7 @@ def timed_solve(P, ctx, prob, prm, net=None, timing=False, start=None):
     if timing:
         for name, kid in (("matvec64", P.native.IPM_KERNEL_MATVEC), ("matvec32", P.native.IPM_KERNEL_MATVEC32),
                           ("resid64", P.native.IPM_KERNEL_RESID64), ("sketch", P.native.IPM_KERNEL_SKETCH),
-                          ("gram", P.native.IPM_KERNEL_GRAM)):
+                          ("gram", P.native.IPM_KERNEL_GRAM), ("warm", P.native.IPM_KERNEL_WARM)):
             kt[name] = ctx.kernel_time(kid)
         ctx.set_timing(False)
     last = res.infos[-1]
@@ -306,6 +306,131 @@ FORM_KEYS = ("converged", "iterations", "seconds", "iter_per_s", "cg_iterations"
              "refine_rounds", "warm_kept", "final_relgap", "final_rp_rel", "final_rd_rel", "objective")
 
 
+def family_setup(family: str, test_lp=None):
+    """(m, n, w, s, storage, make(seed) -> device LP, description) of a warm-start family: LPs that
+    share one A and differ in (b, c)."""
+    from lpgen import device as gdev
+    if family == "illcond_2000x200000":
+        m, n, w, s, storage = 2000, 200_000, 8000, 2, "f32"
+        make = lambda sd: gdev.illcond_lp(m, n, seed=sd, storage=storage)  # noqa: E731
+        desc = ("ill-conditioned A = U diag(sigma) V^T, 2000x200000, sigma log-spaced 1..1e4, FP32 storage "
+                "(FP64 copy for the plain form), w=8000 s=2")
+    else:
+        m, n, w, s, storage = 2000, 2_000_000, 16000, 2, "bf16"
+        base = test_lp if test_lp is not None else gdev.dense_lp(m, n, seed=64, storage=storage, matrix_seed=0)
+        make = lambda sd: gdev.with_seed(base, sd)  # noqa: E731
+        desc = ("dense 2000x2000000 A iid N(0,1) (one A, (b, c) per seed), BF16 storage (FP64 copy for the "
+                "plain form), w=16000 s=2")
+    return m, n, w, s, storage, make, desc
+
+
+def train_warm_start(P, ctx, make, seeds, prm_plain, m: int, epochs: int, tag: str):
+    """Plain-form trajectories of the family's LPs ``seeds``, then the network trained on them (Adam,
+    batch 64, lr 1e-4, width 256): returns (net, training record)."""
+    import torch
+    from paper_2209_08722_amd import learned as L
+    t0 = time.perf_counter()
+    feats, targs, its, cgs = [], [], 0, 0
+    for sd in seeds:
+        lp = make(sd)
+        wide = P.Problem(P.Matrix(lp.A64, lp.n), lp.b, lp.c)
+        tr = L.collect(ctx, [wide], prm_plain)
+        feats.append(tr.X)
+        targs.append(tr.T)
+        its += tr.iterations
+        cgs += tr.cg_iterations
+        log(f"{tag}: training seed {sd}: {tr.iterations} IPM iterations, {tr.cg_iterations} CG iterations")
+        del lp, wide
+    X, T = torch.cat(feats), torch.cat(targs)
+    t_collect = time.perf_counter() - t0
+    net = L.Mlp(m + L.N_EXTRA, 256, m, __import__("lpgen").mlp_init(m + L.N_EXTRA, 256, m, 0, out_scale=1.0))
+    l0 = L.evaluate(ctx, net, X, T)
+    hist = L.train(ctx, net, X, T, epochs=epochs, batch=64, lr=1e-4, seed=0)
+    t_train = time.perf_counter() - t0 - t_collect
+    log(f"{tag}: {X.shape[0]} samples, loss {l0:.3f} -> {hist[-1]:.3f} ({t_collect:.1f} s collecting, "
+        f"{t_train:.1f} s training)")
+    rec = {"seeds": [int(seeds[0]), int(seeds[-1])] if len(seeds) else [], "n_seeds": len(seeds),
+           "samples": int(X.shape[0]), "ipm_iterations": its, "cg_iterations": cgs, "epochs": epochs,
+           "loss_first": l0, "loss_last": hist[-1], "seconds_collect": t_collect, "seconds_train": t_train}
+    del X, T
+    return net, rec
+
+
+def learned_protocol(P, ctx, family: str, n_train: int, n_test: int, epochs: int) -> dict:
+    """The learned warm start's train / held-out protocol: the network is trained on plain-form
+    trajectories of seeds 0..n_train-1 of a family, then every held-out seed n_train..n_train+
+    n_test-1 is solved to the stop test in the plain FP64 and the mixed form from the zero, the
+    previous-dy and the learned start (one whole solve each, same stop test). Reports per seed and
+    in total: IPM and CG iterations, wall time and IPM it/s, and the objective spread."""
+    import torch
+    m, n, w, s, storage, make, desc = family_setup(family)
+    prm = {"plain": P.Params(w=w, s=s, seed=0), "mixed": P.Params(w=w, s=s, seed=0, precision=P.IPM_MIXED)}
+    net, rec = train_warm_start(P, ctx, make, list(range(n_train)), prm["plain"], m, epochs, "protocol")
+    out = {"family": family, "workload": desc, "m": m, "n": n, "w": w, "s": s, "training": rec,
+           "held_out": [n_train, n_train + n_test - 1], "per_seed": []}
+    starts = ("zero", "prev", "learned")
+    tot = {(f, st): {"ipm": 0, "cg": 0, "seconds": 0.0, "warm_kept": 0, "converged": 0,
+                     "warm_ms": 0.0, "warm_launches": 0, "matvec_ms": 0.0, "matvec_launches": 0}
+           for f in prm for st in starts}
+    warmed = False
+    for sd in range(n_train, n_train + n_test):
+        lp = make(sd)
+        probs = {"plain": P.Problem(P.Matrix(lp.A64, n), lp.b, lp.c), "mixed": P.Problem(P.Matrix(lp.A, n), lp.b, lp.c)}
+        if not warmed:
+            for f in prm:   # a few untimed steps per form first (workspaces, code paths)
+                st0 = P.State.initial(m, n)
+                for _ in range(3):
+                    P.ipm_step(ctx, probs[f], st0, prm[f])
+            warmed = True
+        row = {"seed": sd}
+        objs = []
+        for f in prm:
+            for stt in starts:
+                pr = prm[f]
+                if stt == "prev":
+                    from dataclasses import replace
+                    pr = replace(pr, warm_start=P.IPM_WARM_PREV)
+                r = timed_solve(P, ctx, probs[f], pr, net=net if stt == "learned" else None, timing=True)
+                r.pop("_res")
+                t = tot[(f, stt)]
+                for key, kname in (("warm", "warm"), ("matvec", "matvec64")):
+                    ms_, cnt_ = r["kernels"].get(kname, (0.0, 0))
+                    t[f"{key}_ms"] += ms_
+                    t[f"{key}_launches"] += cnt_
+                t["ipm"] += r["iterations"]
+                t["cg"] += r["cg_iterations"]
+                t["seconds"] += r["seconds"]
+                t["warm_kept"] += r["warm_kept"]
+                t["converged"] += int(r["converged"])
+                objs.append(r["objective"])
+                row[f"{f}_{stt}"] = {"ipm": r["iterations"], "cg": r["cg_iterations"], "seconds": r["seconds"],
+                                     "iter_per_s": r["iter_per_s"], "objective": r["objective"],
+                                     "converged": r["converged"], "warm_kept": r["warm_kept"]}
+        row["objective_spread"] = (max(objs) - min(objs)) / (1 + abs(objs[0]))
+        out["per_seed"].append(row)
+        log(f"protocol seed {sd}: " + ", ".join(f"{f}/{stt} CG {row[f'{f}_{stt}']['cg']} "
+                                                 f"({row[f'{f}_{stt}']['iter_per_s']:.2f} it/s)"
+                                                 for f in prm for stt in starts))
+        del lp, probs
+    totals = {}
+    for (f, stt), t in tot.items():
+        totals[f"{f}_{stt}"] = {**t, "iter_per_s": t["ipm"] / t["seconds"] if t["seconds"] > 0 else None,
+                                "cg_per_ipm": t["cg"] / t["ipm"] if t["ipm"] else None,
+                                "warm_ms_per_launch": t["warm_ms"] / t["warm_launches"] if t["warm_launches"] else None,
+                                "matvec_ms_per_launch": (t["matvec_ms"] / t["matvec_launches"]
+                                                         if t["matvec_launches"] else None)}
+    out["totals"] = totals
+    for f in prm:
+        z, pv, ln = (totals[f"{f}_{k}"] for k in starts)
+        out[f"{f}_learned_vs_prev"] = {"cg_saving": 1.0 - ln["cg"] / pv["cg"] if pv["cg"] else None,
+                                       "rate_ratio": ln["iter_per_s"] / pv["iter_per_s"] if pv["iter_per_s"] else None}
+        out[f"{f}_learned_vs_zero"] = {"cg_saving": 1.0 - ln["cg"] / z["cg"] if z["cg"] else None,
+                                       "rate_ratio": ln["iter_per_s"] / z["iter_per_s"] if z["iter_per_s"] else None}
+    out["max_objective_spread"] = max(r["objective_spread"] for r in out["per_seed"]) if out["per_seed"] else None
+    torch.cuda.empty_cache()
+    return out
+
+
 def forms_comparison(P, ctx, family: str, train_seeds: int, epochs: int, test_lp=None, plain=None):
     """The plain FP64 form against the mixed-precision forms (low-precision storage of the same
     values) with zero, previous-dy and learned warm starts on one held-out LP of a family, every
@@ -315,21 +440,8 @@ def forms_comparison(P, ctx, family: str, train_seeds: int, epochs: int, test_lp
     host in FP64 (host_certificate). ``test_lp`` / ``plain``: the held-out LP and its plain-form
     record when the caller already has them."""
     import torch
-    from lpgen import device as gdev
-    from paper_2209_08722_amd import learned as L
-    if family == "illcond_2000x200000":
-        m, n, w, s, storage, test_seed = 2000, 200_000, 8000, 2, "f32", 64
-        make = lambda sd: gdev.illcond_lp(m, n, seed=sd, storage=storage)  # noqa: E731
-        desc = ("ill-conditioned A = U diag(sigma) V^T, 2000x200000, sigma log-spaced 1..1e4, FP32 storage "
-                "(FP64 copy for the plain form), w=8000 s=2")
-    else:
-        m, n, w, s, storage, test_seed = 2000, 2_000_000, 16000, 2, "bf16", 64
-        if test_lp is None:
-            test_lp = gdev.dense_lp(m, n, seed=test_seed, storage=storage, matrix_seed=0)
-        base = test_lp
-        make = lambda sd: gdev.with_seed(base, sd)  # noqa: E731
-        desc = ("dense 2000x2000000 A iid N(0,1) (one A, (b, c) per seed), BF16 storage (FP64 copy for the "
-                "plain form), w=16000 s=2")
+    m, n, w, s, storage, make, desc = family_setup(family, test_lp)
+    test_seed = 64
     prm_plain = P.Params(w=w, s=s, seed=0)
     prm_mixed = P.Params(w=w, s=s, seed=0, precision=P.IPM_MIXED)
 
@@ -337,28 +449,11 @@ def forms_comparison(P, ctx, family: str, train_seeds: int, epochs: int, test_lp
         return P.Problem(P.Matrix(lp.A, lp.n), lp.b, lp.c), P.Problem(P.Matrix(lp.A64, lp.n), lp.b, lp.c)
 
     log(f"forms: training the warm-start network on {train_seeds} plain-form solves ({desc})")
-    t0 = time.perf_counter()
-    feats, targs = [], []
-    for sd in range(train_seeds):
-        lp = make(sd)
-        _, wide = problems(lp)
-        tr = L.collect(ctx, [wide], prm_plain)
-        feats.append(tr.X)
-        targs.append(tr.T)
-        log(f"forms: training seed {sd}: {tr.iterations} IPM iterations, {tr.cg_iterations} CG iterations")
-        del lp, wide
-    X, T = torch.cat(feats), torch.cat(targs)
-    net = L.Mlp(m + L.N_EXTRA, 256, m, __import__("lpgen").mlp_init(m + L.N_EXTRA, 256, m, 0, out_scale=1.0))
-    l0 = L.evaluate(ctx, net, X, T)
-    hist = L.train(ctx, net, X, T, epochs=epochs, batch=64, lr=1e-4, seed=0)
-    t_train = time.perf_counter() - t0
-    log(f"forms: {X.shape[0]} samples, loss {l0:.3f} -> {hist[-1]:.3f} in {t_train:.1f} s")
+    net, rec = train_warm_start(P, ctx, make, list(range(train_seeds)), prm_plain, m, epochs, "forms")
 
     lp = test_lp if test_lp is not None else make(test_seed)
     low, wide = problems(lp)
-    out = {"workload": desc, "m": m, "n": n, "w": w, "s": s, "test_seed": test_seed,
-           "training": {"seeds": train_seeds, "samples": int(X.shape[0]), "epochs": epochs,
-                        "loss_first": l0, "loss_last": hist[-1], "seconds": t_train}}
+    out = {"workload": desc, "m": m, "n": n, "w": w, "s": s, "test_seed": test_seed, "training": rec}
     runs = [("plain_fp64", wide, prm_plain, None), ("mixed", low, prm_mixed, None),
             ("mixed_prev", low, P.Params(w=w, s=s, seed=0, precision=P.IPM_MIXED, warm_start=P.IPM_WARM_PREV), None),
             ("mixed_learned", low, prm_mixed, net),
@@ -582,6 +677,11 @@ def main() -> int:
                     help="family of the plain vs mixed+learned comparison (auto: the 2000x2000000 workload itself "
                          "when it is the benchmark's, else none)")
     ap.add_argument("--train-seeds", type=int, default=2)
+    ap.add_argument("--learned-protocol", default="", choices=["", "illcond_2000x200000", "dense_2000x2000000"],
+                    help="only run the learned warm start's train / held-out protocol on this family "
+                         "(--protocol-train seeds for training, the next --protocol-test held out)")
+    ap.add_argument("--protocol-train", type=int, default=64)
+    ap.add_argument("--protocol-test", type=int, default=16)
     ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
@@ -620,6 +720,11 @@ def main() -> int:
         return kernel_only(args)
     import lpgen
     import paper_2209_08722_amd as P
+    if args.learned_protocol:
+        ctx = P.Context(0)
+        res = learned_protocol(P, ctx, args.learned_protocol, args.protocol_train, args.protocol_test, args.epochs)
+        print(json.dumps(res))
+        return 0
 
     wl = WORKLOADS[args.workload]
     m, n, w, s = wl["m"], wl["n"], wl["w"], wl["s"]

@@ -287,7 +287,9 @@ int ipm_step(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_
  * candidate vectors dy0 [device, ncand x m doubles, one vector after the other], used when
  * params->warm_start is IPM_WARM_GIVEN (the learned warm start passes the previous dy and the
  * network's output). Two candidates nearly parallel in the M-norm (squared sine of their angle
- * below 1e-8) are reduced to the first. dy0 is read only. */
+ * below 1e-8) are reduced to the first. The candidates' products M dy0_k come from one pass
+ * over A for both (FP64 accumulation), computed once per step and shared by every draw of W.
+ * dy0 is read only. */
 int ipm_step_warm(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm_params* params,
                   const double* dy0, int32_t ncand, ipm_step_info* info);
 
@@ -396,7 +398,8 @@ int ipm_stream_copy(ipm_ctx* ctx, const void* src, void* dst, int64_t bytes);
 #define IPM_KERNEL_RESID64 4   /* the mixed form's FP64-accumulated residual pass          */
 #define IPM_KERNEL_STREAM_READ 5  /* the read pass of ipm_stream_read                       */
 #define IPM_KERNEL_STREAM_COPY 6  /* the copy pass of ipm_stream_copy                       */
-#define IPM_KERNEL_COUNT   7
+#define IPM_KERNEL_WARM    7   /* the warm start's candidate products (one pass for both)  */
+#define IPM_KERNEL_COUNT   8
 
 /* Per-kernel timing with HIP events recorded at the start and end of launches of the kernels
  * above on the context's stream: on = 0 disables it; on = N >= 1 times every N-th launch of each

@@ -451,7 +451,7 @@ int run_pass(ipm_ctx* ctx, const ipm_matrix* A, StripCall& c, int kernel_id, int
     c.m = (int)A->m;
     c.n = A->n;
     c.ld = A->ld;
-    const int nacc = c.kind == STRIP_RESID ? 2 : 1;
+    const int nacc = strip_nacc(c.kind);
     CHK(ws(ctx, W_GPART, (size_t)rowsum_blocks(c.m), &c.gpart));
     if (A->layout == IPM_CSR) {
         c.row_ptr = A->row_ptr;
@@ -491,6 +491,30 @@ int matvec_pass(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const doubl
     c.out0 = out;
     c.done = done;
     return run_pass(ctx, A, c, acc64 || A->dtype == IPM_F64 ? IPM_KERNEL_MATVEC : IPM_KERNEL_MATVEC32, tag);
+}
+
+// The warm start's candidate products q_k <- A diag(d2) A^T v_k (k < ncand <= 2), FP64
+// accumulation: two candidates share one pass over A (each vector's dots and row sums in the
+// order the single-vector pass uses). Where the shared memory of the dense pass cannot hold both
+// vectors (BF16 re-read form beyond about 4800 rows) it runs one pass per vector.
+int warm_products(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* v0, const double* v1, int ncand,
+                  double* q0, double* q1) {
+    const bool pair = ncand > 1 &&
+                      (A->layout == IPM_CSR || strip_plan(A->dtype, (int)A->m, A->n, ctx->num_cu, STRIP_MATVEC2).nt > 0);
+    for (int k = 0; k < (ncand > 1 && !pair ? 2 : 1); ++k) {
+        StripCall c{};
+        c.kind = pair ? STRIP_MATVEC2 : STRIP_MATVEC;
+        c.acc64 = 1;
+        c.post = pair ? POST_PAIR : POST_PLAIN;
+        c.vec0 = k == 0 ? v0 : v1;
+        c.vec1 = pair ? v1 : nullptr;
+        c.d2 = d2;
+        c.out0 = k == 0 ? q0 : q1;
+        c.out1 = pair ? q1 : nullptr;
+        CHK(run_pass(ctx, A, c, IPM_KERNEL_WARM, -1));
+    }
+    resolve_timing(ctx, IPM_KERNEL_WARM, INT_MAX);
+    return IPM_OK;
 }
 
 // r <- p - A diag(d2) A^T dy with FP64 accumulation whatever the storage type of A (the true
@@ -563,20 +587,24 @@ void tridiag_extremes(const double* d, const double* e, int k, double* lo, doubl
 
 // Initial iterate from ncand (1 or 2) candidate vectors cand[0:m], cand[m:2m]: their
 // M-norm-optimal combination into dy_out, M dy_out into q_out and, if r_out is given,
-// p - M dy_out into r_out. The matvecs accumulate in FP64 when acc64 is set.
+// p - M dy_out into r_out. The products accumulate in FP64, one pass over A for both candidates.
 int warm_combination(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* p, const double* cand,
-                     int ncand, int acc64, double* dy_out, double* q_out, double* r_out) {
+                     int ncand, double* dy_out, double* q_out, double* r_out) {
     const int m = (int)A->m;
     double* q2 = nullptr;
-    CHK(matvec_pass(ctx, A, d2, cand, q_out, nullptr, -1, acc64));
-    if (ncand > 1) {
-        CHK(ws(ctx, W_WQ, (size_t)m, &q2));
-        CHK(matvec_pass(ctx, A, d2, cand + m, q2, nullptr, -1, acc64));
-    }
+    if (ncand > 1) CHK(ws(ctx, W_WQ, (size_t)m, &q2));
+    CHK(warm_products(ctx, A, d2, cand, ncand > 1 ? cand + m : nullptr, ncand, q_out, q2));
     HIPCHK(launch_warm_galerkin(m, ncand, cand, ncand > 1 ? cand + m : nullptr, p, q_out, q2, dy_out, q_out, r_out,
                                 ctx->stream));
     return IPM_OK;
 }
+
+// A warm start of the CG solve: the candidates' combination dy and q = M dy. It depends on A, D
+// and p only, so one IPM step computes it once for all of its draws of W.
+struct WarmStart {
+    const double* dy;
+    const double* q;
+};
 
 // Chebyshev iteration (Section 3.2) continuing the CG probe held in b (iterate dy[k & 1],
 // residual r[k & 1] after k = out->iters steps): the interval comes from the probe's Lanczos
@@ -660,12 +688,12 @@ int chebyshev_stage(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, PcgBufs
     return IPM_OK;
 }
 
-// CG with preconditioner X^T X (X = L^{-1}); dy_out receives the solution. With ncand > 0 the
-// solve starts from the combination of the candidate vectors (kept only if its preconditioned
-// residual is below that of the zero start); cand may alias dy_out when ncand is 1.
+// CG with preconditioner X^T X (X = L^{-1}); dy_out receives the solution. With a warm start the
+// solve starts from its combination (kept only if its preconditioned residual is below that of
+// the zero start).
 int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X, const double* p, double* dy_out,
-           const double* cand, int ncand, const ipm_params* prm, const PcgCfg& cfg, PcgOut* out) {
-    const int warm = ncand > 0 ? 1 : 0;
+           const WarmStart* w0, const ipm_params* prm, const PcgCfg& cfg, PcgOut* out) {
+    const int warm = w0 != nullptr ? 1 : 0;
     hipStream_t st = ctx->stream;
     const int m = (int)A->m;
     double* XT = nullptr;
@@ -704,9 +732,12 @@ int do_pcg(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X,
     b.maxit = cg_maxit;
     b.ahist = cheb ? cd + PD_HIST + cfg.maxit + 2 : nullptr;
     HIPCHK(launch_fill_i32(ci, PI_COUNT, 0, st));
-    if (warm) CHK(warm_combination(ctx, A, d2, p, cand, ncand, cfg.acc64, dy_out, b.q, nullptr));
-    HIPCHK(launch_pcg_init1(b, warm, st));
-    HIPCHK(launch_pcg_init2(b, warm, dy_out, st));
+    {
+        PcgBufs bi = b;   // the start's M dy0 in place of the matvec output
+        if (warm) bi.q = const_cast<double*>(w0->q);   // read only by the start kernels
+        HIPCHK(launch_pcg_init1(bi, warm, st));
+        HIPCHK(launch_pcg_init2(bi, warm, warm ? w0->dy : nullptr, st));
+    }
     double* hd = reinterpret_cast<double*>(ctx->pinned);
     int j = 0;
     // first batch: the previous solve's iteration count (CG counts change slowly between IPM
@@ -756,31 +787,31 @@ int precond_norm2(ipm_ctx* ctx, const double* X, int m, const double* v, double*
 // that does not shrink the residual by half (FP32 accumulation error comparable to the
 // preconditioned system's scale, late in the IPM) switches the inner solves to FP64 accumulation.
 int do_pcg_mixed(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const double* X, const double* p,
-                 double* dy, const double* cand, int ncand, const ipm_params* prm, PcgOut* out) {
+                 double* dy, const WarmStart* w0, const ipm_params* prm, PcgOut* out) {
     hipStream_t st = ctx->stream;
     const int m = (int)A->m;
     double *ref = nullptr, *XT = nullptr;
     CHK(ws(ctx, W_REF, (size_t)4 * m + 8, &ref));
     CHK(ws(ctx, W_XT, (size_t)m * m, &XT));
     double* r = ref;             // true residual p - M dy
-    double* delta = ref + m;     // inner solution (and M dy0 for the warm start)
+    double* delta = ref + m;     // inner solution
     double* g = ref + 2 * m;     // X v
-    double* dyw = ref + 3 * m;   // scaled warm start
     double* sc = ref + 4 * m;    // [0] ||X p||^2, [1] ||X r||^2, [2] ||X r0||^2 (warm start)
     double* hd = reinterpret_cast<double*>(ctx->pinned) + 64;
     HIPCHK(launch_transpose(X, XT, m, st));
     CHK(precond_norm2(ctx, X, m, p, g, sc));
     out->warm_used = 0;
-    if (ncand > 0) {
-        // M-norm-optimal combination of the candidates and its residual, FP64 accumulation
-        CHK(warm_combination(ctx, A, d2, p, cand, ncand, 1, dyw, delta, r));
+    if (w0) {
+        // residual of the candidates' combination (its product accumulated in FP64)
+        HIPCHK(hipMemcpyAsync(r, p, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+        HIPCHK(launch_axpy(m, -1.0, w0->q, r, st));
         CHK(precond_norm2(ctx, X, m, r, g, sc + 2));
         HIPCHK(hipMemcpyAsync(hd, sc, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         out->warm_used = hd[2] < hd[0] ? 1 : 0;
     }
     if (out->warm_used) {
-        HIPCHK(hipMemcpyAsync(dy, dyw, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(dy, w0->dy, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
     } else {
         HIPCHK(launch_fill(dy, m, 0.0, st));
         HIPCHK(hipMemcpyAsync(r, p, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
@@ -820,7 +851,7 @@ int do_pcg_mixed(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const doub
         cfg.xt_ready = true;
         cfg.last_iters = fp64_inner ? &ctx->last_pcg_iters : &ctx->last_inner_iters;
         PcgOut io{};
-        CHK(do_pcg(ctx, A, d2, X, r, delta, nullptr, 0, prm, cfg, &io));
+        CHK(do_pcg(ctx, A, d2, X, r, delta, nullptr, prm, cfg, &io));
         total += io.iters;
         ++rounds;
         if (io.status == IPM_ERR_BREAKDOWN) {
@@ -1035,20 +1066,21 @@ int ipm_pcg_solve(ipm_ctx* ctx, const ipm_matrix* A, const double* d2, const dou
     CHK(check_solver_params(ctx, params));
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, IPM_ERR_HIP, "hipSetDevice failed");
     PcgOut o{};
+    // the caller's dy scaled to its M-norm-optimal multiple (FP64 accumulation)
+    WarmStart w0s{};
+    if (warm) {
+        double* wb = nullptr;
+        CHK(ws(ctx, W_WARM, (size_t)2 * A->m, &wb));
+        CHK(warm_combination(ctx, A, d2, p, dy, 1, wb, wb + A->m, nullptr));
+        w0s = WarmStart{wb, wb + A->m};
+    }
+    const WarmStart* w0 = warm ? &w0s : nullptr;
     if (params->precision == IPM_MIXED_F32ACC) {
-        const int m = (int)A->m;
-        const double* dy0 = nullptr;
-        if (warm) {
-            double* w0 = nullptr;
-            CHK(ws(ctx, W_WARM, (size_t)m, &w0));
-            HIPCHK(hipMemcpyAsync(w0, dy, sizeof(double) * m, hipMemcpyDeviceToDevice, ctx->stream));
-            dy0 = w0;
-        }
-        CHK(do_pcg_mixed(ctx, A, d2, Linv, p, dy, dy0, dy0 ? 1 : 0, params, &o));
+        CHK(do_pcg_mixed(ctx, A, d2, Linv, p, dy, w0, params, &o));
     } else {
         PcgCfg cfg{params->tol_pcg, params->maxit_pcg, 1, false, &ctx->last_pcg_iters};
         cfg.cheb_probe = params->solver == IPM_SOLVER_CHEBYSHEV ? kChebProbe : 0;
-        CHK(do_pcg(ctx, A, d2, Linv, p, dy, warm ? dy : nullptr, warm ? 1 : 0, params, cfg, &o));
+        CHK(do_pcg(ctx, A, d2, Linv, p, dy, w0, params, cfg, &o));
     }
     if (info) {
         info->iters = o.iters;
@@ -1251,6 +1283,16 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
         dy0 = reinterpret_cast<const double*>(ctx->ws[W_PREV]);
         ncand = 1;
     }
+    // their M-norm-optimal combination and its product (one pass over A for both candidates,
+    // FP64 accumulation), shared by every draw
+    WarmStart w0s{};
+    if (ncand > 0) {
+        double* wb = nullptr;
+        CHK(ws(ctx, W_WARM, (size_t)2 * m, &wb));
+        CHK(warm_combination(ctx, A, d2, p, dy0, ncand, wb, wb + m, nullptr));
+        w0s = WarmStart{wb, wb + m};
+    }
+    const WarmStart* w0 = ncand > 0 ? &w0s : nullptr;
 
     // Algorithm 1 with redraws of W: sketch, factor, CG. The mixed form keeps a sparse sketch's B
     // in FP32; the Gaussian sketch (an MFMA product) produces B in FP64 in every form.
@@ -1300,11 +1342,11 @@ int step_impl(ipm_ctx* ctx, const ipm_problem* prob, ipm_state* state, const ipm
             continue;
         }
         if (refine) {
-            CHK(do_pcg_mixed(ctx, A, d2, X, p, dyv, dy0, ncand, prm, &po));
+            CHK(do_pcg_mixed(ctx, A, d2, X, p, dyv, w0, prm, &po));
         } else {
             PcgCfg cfg{prm->tol_pcg, prm->maxit_pcg, 1, false, &ctx->last_pcg_iters};
             cfg.cheb_probe = prm->solver == IPM_SOLVER_CHEBYSHEV ? kChebProbe : 0;
-            CHK(do_pcg(ctx, A, d2, X, p, dyv, dy0, ncand, prm, cfg, &po));
+            CHK(do_pcg(ctx, A, d2, X, p, dyv, w0, prm, cfg, &po));
         }
         if (po.status == IPM_ERR_BREAKDOWN) {
             info->status = IPM_ERR_BREAKDOWN;

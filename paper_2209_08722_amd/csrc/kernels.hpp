@@ -13,10 +13,16 @@ enum Scalar {
 };
 
 // Post-processing of the row reduction of strip-pass partials.
-enum RowPost { POST_PLAIN = 0, POST_MATVEC = 1, POST_RESID = 2, POST_RHAT = 3, POST_RESP = 4, POST_SUBR = 5 };
+enum RowPost {
+    POST_PLAIN = 0, POST_MATVEC = 1, POST_RESID = 2, POST_RHAT = 3, POST_RESP = 4, POST_SUBR = 5,
+    POST_PAIR = 6   // both accumulations stored: out0, out1
+};
 
 // Kinds of single-pass strip kernels over row-major A.
-enum StripKind { STRIP_MATVEC = 0, STRIP_RESID = 1, STRIP_DIR = 2 };
+enum StripKind { STRIP_MATVEC = 0, STRIP_RESID = 1, STRIP_DIR = 2, STRIP_MATVEC2 = 3 };
+
+// Row accumulations (outputs) of a pass of this kind.
+inline int strip_nacc(int kind) { return (kind == STRIP_RESID || kind == STRIP_MATVEC2) ? 2 : 1; }
 
 struct StripPlan {
     int nt;        // threads per block
@@ -41,6 +47,7 @@ struct StripCall {
     int m;
     int64_t n, ld;
     const double* vec0;      // m-vector dotted with every column
+    const double* vec1;      // m (matvec2: the second vector)
     const double* d2;        // n: diagonal of D^2
     const double* x;         // n (resid)
     const double* s;         // n (resid)

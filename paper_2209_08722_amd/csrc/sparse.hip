@@ -2,7 +2,8 @@
 // configurations: a few nonzeros per column, about a thousand per row).
 //
 // Every pass over A has the two halves of the dense strip pass (strip.hip), here as two kernels:
-//   column pass (CSC): t_j = a_j^T vec0, then the per-column step of the pass (strip_ops.hpp),
+//   column pass (CSC): t_j = a_j^T vec0 (and a_j^T vec1 for the paired matvec), then the
+//                      per-column step of the pass (strip_ops.hpp),
 //                      writing the column coefficients to an n-vector workspace;
 //   row pass (CSR):    q_i = sum_j a_ij coef_j, then the row post step (plain, residual, true
 //                      residual, p - q), one wave per row.
@@ -26,14 +27,21 @@ __device__ __forceinline__ double elem(const void* v, int64_t k) {
 template <typename T, class Op>
 __global__ __launch_bounds__(CNT) void k_csc_cols(StripCall a) {
     if (a.done != nullptr && *a.done) return;
-    constexpr int NA = Op::NACC, NCR = Op::NCR;
+    constexpr int NA = Op::NACC, NCR = Op::NCR, ND = Op::ND;
     __shared__ double sh[CNT / 64];
     const typename Op::S st = Op::init(a);
     double cr[NCR > 0 ? NCR : 1] = {0.0};
     for (int64_t j = (int64_t)blockIdx.x * CNT + threadIdx.x; j < a.n; j += (int64_t)gridDim.x * CNT) {
         const int64_t k0 = a.col_ptr[j], k1 = a.col_ptr[j + 1];
-        double t = 0.0;
-        for (int64_t k = k0; k < k1; ++k) t += elem<T>(a.csc_val, k) * a.vec0[a.row_idx[k]];
+        double t[ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) t[d] = 0.0;
+        for (int64_t k = k0; k < k1; ++k) {
+            const double v = elem<T>(a.csc_val, k);
+            const int32_t i = a.row_idx[k];
+            t[0] += v * a.vec0[i];
+            if constexpr (ND > 1) t[1] += v * a.vec1[i];
+        }
         double cf[NA];
         Op::template column<double>(a, st, j, true, true, t, cf, cr, Op::PF ? Op::pre(a, j, true) : 0.0);
 #pragma unroll
@@ -83,6 +91,7 @@ __global__ __launch_bounds__(RNT_S) void k_csr_rows(StripCall a, int nacc, int n
                 case POST_RHAT: a.out0[i] = t0 - a.pvec[i]; break;
                 case POST_RESP: a.out0[i] = a.pvec[i] - t0; break;
                 case POST_SUBR: a.out0[i] -= t0; break;   // r -= M dx (Chebyshev)
+                case POST_PAIR: a.out0[i] = t0; a.out1[i] = t1; break;
                 default: break;
             }
         }
@@ -175,6 +184,7 @@ hipError_t launch_sparse_pass(const StripCall& c, hipStream_t st) {
         case STRIP_MATVEC: return sparse_type<OpMatvec>(c, st);
         case STRIP_RESID: return sparse_type<OpResid>(c, st);
         case STRIP_DIR: return sparse_type<OpDir>(c, st);
+        case STRIP_MATVEC2: return sparse_type<OpMatvec2>(c, st);
         default: return hipErrorInvalidValue;
     }
 }

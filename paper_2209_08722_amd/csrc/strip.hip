@@ -1,7 +1,8 @@
 // Single-pass column-strip kernels over row-major A (m x n, row stride ld).
 //
-// Every pass here has the shape "per column j: dot a_j with one m-vector, turn the dots into
-// per-column coefficients; per row i: accumulate sum_j A[i][j] * coef_j". Reading A once per
+// Every pass here has the shape "per column j: dot a_j with one m-vector (two for the paired
+// matvec), turn the dots into per-column coefficients; per row i: accumulate
+// sum_j A[i][j] * coef_j" (one or two accumulations). Reading A once per
 // pass requires each column strip to stay on chip between the dot and the accumulation, so a
 // block owns a strip of SW columns across all m rows, held in registers:
 //   - lanes: LPR lanes per row, 16-byte vector loads -> LPR*16 contiguous bytes per row segment;
@@ -18,7 +19,8 @@
 //     post-processing step (r_p, p, the true residual, ...).
 // The CG matvec q = A D^2 A^T v (Algorithm 1, step 3) is one such pass; so are the residual
 // pass (r_d = A^T y + s - c, then A x and A u for r_p and p, Section 5 / Algorithm 3 step 3) and
-// the direction pass (ds = -r_d - A^T dy, then A D^2 A^T dy for the true residual).
+// the direction pass (ds = -r_d - A^T dy, then A D^2 A^T dy for the true residual); the paired
+// matvec A D^2 A^T [v0 v1] (the warm start's two candidate products) reads A once for both.
 #include "strip_ops.hpp"
 
 namespace ipmsk {
@@ -100,6 +102,7 @@ __global__ __launch_bounds__(RNT) void k_rowsum(StripCall a, int G, int nacc, in
                 case POST_RHAT: a.out0[i] = t0 - a.pvec[i]; break;
                 case POST_RESP: a.out0[i] = a.pvec[i] - t0; break;
                 case POST_SUBR: a.out0[i] -= t0; break;   // r -= M dx (Chebyshev)
+                case POST_PAIR: a.out0[i] = t0; a.out1[i] = t1; break;
                 default: break;
             }
         }
@@ -123,24 +126,28 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     constexpr int SW = LPR * VEC;
     constexpr int RG = NT / LPR;
     constexpr int NW = NT / 64;
-    constexpr int NA = Op::NACC, NCR = Op::NCR;
+    constexpr int NA = Op::NACC, NCR = Op::NCR, ND = Op::ND;
     constexpr int MPAD = RG * RPT;
 
     if (a.done != nullptr && *a.done) return;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    ACC* vs = reinterpret_cast<ACC*>(smem_raw);   // [MPAD]        vector dotted with columns
-    ACC* red = vs + MPAD;                            // [2][NW][SW]   per-wave column dots
+    ACC* vs = reinterpret_cast<ACC*>(smem_raw);   // [ND][MPAD]        vectors dotted with columns
+    ACC* red = vs + ND * MPAD;                       // [2][ND][NW][SW]   per-wave column dots
     // QL row sums [NA][RPT][RG + 8]: row g + RG k at k (RG + 8) + g; the padding puts the eight
     // rows a wave's lane c of eight row groups add at once into distinct bank pairs but for c
     // and c + 4
     constexpr int QS_K = RG + 8, QS_A = RPT * QS_K;
     // FP32 storage with FP64 accumulation (four conversions per word) has no registers left for
     // the reduce-scatter's partial sums at 32 rows per thread in the residual and direction
-    // passes; there it sums each row on its own (the CG matvec, with its buffer-loaded rolling
-    // strip, keeps the reduce-scatter)
+    // passes; there it sums each row on its own (the matvec passes, whose strips are read with
+    // buffer loads, keep the reduce-scatter)
     constexpr bool RS = (QL && Op::PF) || !(sizeof(T) == 4 && sizeof(ACC) == 8 && RPT > 24);
-    double* qs = reinterpret_cast<double*>(red + 2 * NW * SW);
+    // the paired pass over FP32 storage reads whole strips with buffer loads: per-row 64-bit
+    // addresses held across the strip loop spill at this register count (FP64 and BF16 storage
+    // are faster with the per-row loads)
+    constexpr bool BUFLD = QL && ND > 1 && sizeof(T) == 4 && sizeof(ACC) == 8;
+    double* qs = reinterpret_cast<double*>(red + 2 * ND * NW * SW);
     __shared__ double shr[NW];
 
     const int tid = threadIdx.x;
@@ -149,7 +156,10 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     const int G = gridDim.x;
     const T* __restrict__ A = reinterpret_cast<const T*>(a.A);
 
-    for (int i = tid; i < MPAD; i += NT) vs[i] = (i < m) ? (ACC)a.vec0[i] : (ACC)0;
+    for (int i = tid; i < MPAD; i += NT) {
+        vs[i] = (i < m) ? (ACC)a.vec0[i] : (ACC)0;
+        if constexpr (ND > 1) vs[MPAD + i] = (i < m) ? (ACC)a.vec1[i] : (ACC)0;
+    }
     if constexpr (QL) {
         for (int i = tid; i < NA * QS_A; i += NT) qs[i] = 0.0;
     }
@@ -179,7 +189,7 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     // streams in during this strip's accumulation and the next strip's column dots. Whole strips
     // are read with buffer loads (load_group_row); the host keeps each row group's byte offsets
     // below 2^32.
-    constexpr bool ROLL = QL && RS && Op::PF;
+    constexpr bool ROLL = QL && RS && Op::PF && ND == 1;
     const int64_t rowstride = (int64_t)RG * a.ld;
     const uint32_t lane_bytes = lane_off * (uint32_t)sizeof(T);
     const uint32_t group_bytes = (uint32_t)((int64_t)RG * a.ld * (int64_t)sizeof(T));
@@ -213,39 +223,59 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
         if constexpr (!ROLL) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) pfv[e] = Op::PF ? Op::pre(a, j0 + e, j0 + e < a.n) : 0.0;
-            load_segment<T, RPT, true>(A + (int64_t)strip * SW + lane_off, A + (int64_t)strip * SW + c * VEC,
-                                       rowstride, g, RG, m, a.n - j0, av);
+            if (BUFLD && whole(strip)) {
+#pragma unroll
+                for (int k = 0; k < RPT; ++k)
+                    av[k] = load_group_row(A + (int64_t)strip * SW + (int64_t)k * rowstride, group_nrec(k), lane_bytes);
+            } else {
+                load_segment<T, RPT, true>(A + (int64_t)strip * SW + lane_off, A + (int64_t)strip * SW + c * VEC,
+                                           rowstride, g, RG, m, a.n - j0, av);
+            }
         }
-        // column dots over this thread's rows
-        ACC pd[VEC];
+        // column dots over this thread's rows, one vector after the other, then over the 64/LPR
+        // row groups of this wave (lane bits log2(LPR)..5)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) pd[e] = (ACC)0;
+        for (int d = 0; d < ND; ++d) {
+            ACC pd[VEC];
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const ACC vv = vs[g + RG * k];
+            for (int e = 0; e < VEC; ++e) pd[e] = (ACC)0;
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) pd[e] += Elem<T>::template get<ACC>(av[k], e) * vv;
-        }
-        // over the 64/LPR row groups of this wave (lane bits log2(LPR)..5)
+            for (int k = 0; k < RPT; ++k) {
+                const ACC vv = vs[d * MPAD + g + RG * k];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            ACC v = pd[e];
+                for (int e = 0; e < VEC; ++e) pd[e] += Elem<T>::template get<ACC>(av[k], e) * vv;
+            }
 #pragma unroll
-            for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-            pd[e] = v;
-        }
-        ACC* rb = red + buf * NW * SW;
-        if (lane < LPR) {
+            for (int e = 0; e < VEC; ++e) {
+                ACC v = pd[e];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) rb[wid * SW + c * VEC + e] = pd[e];
+                for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+                pd[e] = v;
+            }
+            if (lane < LPR) {
+                ACC* rw = red + (buf * ND + d) * NW * SW;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) rw[wid * SW + c * VEC + e] = pd[e];
+            }
+            if constexpr (ND > 1) {
+                // the next vector converts the raw words again (see below)
+#pragma unroll
+                for (int k = 0; k < RPT; ++k)
+                    asm volatile("" : "+v"(av[k].x), "+v"(av[k].y), "+v"(av[k].z), "+v"(av[k].w));
+            }
         }
         __syncthreads();
+        const ACC* rb = red + buf * ND * NW * SW;
         ACC coef[NA][VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            ACC t = (ACC)0;
+            ACC t[ND];
 #pragma unroll
-            for (int w = 0; w < NW; ++w) t += rb[w * SW + c * VEC + e];
+            for (int d = 0; d < ND; ++d) {
+                t[d] = (ACC)0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t[d] += rb[(d * NW + w) * SW + c * VEC + e];
+            }
             ACC cf[NA];
             const int64_t j = j0 + e;
             Op::template column<ACC>(a, st, j, j < a.n, g == 0, t, cf, cr, pfv[e]);
@@ -382,20 +412,23 @@ __global__ __launch_bounds__(NT) void k_strip_rr(StripCall a, int nstrips, int K
     constexpr int SW = LPR * VEC;
     constexpr int RG = NT / LPR;
     constexpr int NW = NT / 64;
-    constexpr int NA = Op::NACC, NCR = Op::NCR;
+    constexpr int NA = Op::NACC, NCR = Op::NCR, ND = Op::ND;
     if (a.done != nullptr && *a.done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int MPAD = RG * K;
-    ACC* vs = reinterpret_cast<ACC*>(smem_raw);                        // [MPAD]
-    ACC* red = vs + MPAD;                                               // [2][NW][SW]
-    double* qs = reinterpret_cast<double*>(red + 2 * NW * SW);         // [NA][MPAD]
+    ACC* vs = reinterpret_cast<ACC*>(smem_raw);                        // [ND][MPAD]
+    ACC* red = vs + ND * MPAD;                                          // [2][ND][NW][SW]
+    double* qs = reinterpret_cast<double*>(red + 2 * ND * NW * SW);    // [NA][MPAD]
     __shared__ double shr[NW];
     const int tid = threadIdx.x;
     const int c = tid % LPR, g = tid / LPR, lane = tid & 63, wid = tid >> 6;
     const int m = a.m;
     const int G = gridDim.x;
     const T* __restrict__ A = reinterpret_cast<const T*>(a.A);
-    for (int i = tid; i < MPAD; i += NT) vs[i] = (i < m) ? (ACC)a.vec0[i] : (ACC)0;
+    for (int i = tid; i < MPAD; i += NT) {
+        vs[i] = (i < m) ? (ACC)a.vec0[i] : (ACC)0;
+        if constexpr (ND > 1) vs[MPAD + i] = (i < m) ? (ACC)a.vec1[i] : (ACC)0;
+    }
     for (int i = tid; i < NA * MPAD; i += NT) qs[i] = 0.0;
     __syncthreads();
     const typename Op::S st = Op::init(a);
@@ -408,40 +441,52 @@ __global__ __launch_bounds__(NT) void k_strip_rr(StripCall a, int nstrips, int K
         double pfv[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) pfv[e] = Op::PF ? Op::pre(a, j0 + e, j0 + e < a.n) : 0.0;
-        ACC pd[VEC];
+        ACC pd[ND][VEC];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) pd[e] = (ACC)0;
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) pd[d][e] = (ACC)0;
         for (int k0 = 0; k0 < K; k0 += CH) {
             uint4 av[CH];
             load_segment<T, CH, false>(A + (int64_t)strip * SW + (int64_t)(RG * k0) * a.ld + lane_off,
                                        A + (int64_t)strip * SW + c * VEC, (int64_t)RG * a.ld, g + RG * k0, RG, m,
                                        left, av);
 #pragma unroll
-            for (int kk = 0; kk < CH; ++kk) {
-                const ACC vv = vs[g + RG * (k0 + kk)];
+            for (int kk = 0; kk < CH; ++kk)
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) pd[e] += Elem<T>::template get<ACC>(av[kk], e) * vv;
+                for (int d = 0; d < ND; ++d) {
+                    const ACC vv = vs[d * MPAD + g + RG * (k0 + kk)];
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) pd[d][e] += Elem<T>::template get<ACC>(av[kk], e) * vv;
+                }
+        }
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                ACC v = pd[d][e];
+#pragma unroll
+                for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+                pd[d][e] = v;
             }
-        }
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            ACC v = pd[e];
-#pragma unroll
-            for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-            pd[e] = v;
-        }
-        ACC* rb = red + buf * NW * SW;
+        ACC* rb = red + buf * ND * NW * SW;
         if (lane < LPR) {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) rb[wid * SW + c * VEC + e] = pd[e];
+            for (int d = 0; d < ND; ++d)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) rb[(d * NW + wid) * SW + c * VEC + e] = pd[d][e];
         }
         __syncthreads();
         ACC coef[NA][VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            ACC t = (ACC)0;
+            ACC t[ND];
 #pragma unroll
-            for (int w = 0; w < NW; ++w) t += rb[w * SW + c * VEC + e];
+            for (int d = 0; d < ND; ++d) {
+                t[d] = (ACC)0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t[d] += rb[(d * NW + w) * SW + c * VEC + e];
+            }
             ACC cf[NA];
             const int64_t j = j0 + e;
             Op::template column<ACC>(a, st, j, j < a.n, g == 0, t, cf, cr, pfv[e]);
@@ -520,11 +565,24 @@ hipError_t dispatch_nt(const StripCall& c, const StripPlan& p, hipStream_t st) {
 
 template <class Op>
 hipError_t dispatch_type(const StripCall& c, const StripPlan& p, hipStream_t st) {
-    switch (c.dtype) {
-        case 0: return dispatch_nt<double, double, Op>(c, p, st);
-        case 1: return c.acc64 ? dispatch_nt<float, double, Op>(c, p, st) : dispatch_nt<float, float, Op>(c, p, st);
-        case 2: return c.acc64 ? dispatch_nt<bf16_t, double, Op>(c, p, st) : dispatch_nt<bf16_t, float, Op>(c, p, st);
-        default: return hipErrorInvalidValue;
+    if constexpr (Op::ND > 1) {
+        // the paired pass (the warm start's products) accumulates in FP64 only
+        if (!c.acc64) return hipErrorInvalidValue;
+        switch (c.dtype) {
+            case 0: return dispatch_nt<double, double, Op>(c, p, st);
+            case 1: return dispatch_nt<float, double, Op>(c, p, st);
+            case 2: return dispatch_nt<bf16_t, double, Op>(c, p, st);
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (c.dtype) {
+            case 0: return dispatch_nt<double, double, Op>(c, p, st);
+            case 1:
+                return c.acc64 ? dispatch_nt<float, double, Op>(c, p, st) : dispatch_nt<float, float, Op>(c, p, st);
+            case 2:
+                return c.acc64 ? dispatch_nt<bf16_t, double, Op>(c, p, st) : dispatch_nt<bf16_t, float, Op>(c, p, st);
+            default: return hipErrorInvalidValue;
+        }
     }
 }
 
@@ -541,8 +599,8 @@ int rowsum_blocks(int m) { return (m + RNT / 64 - 1) / (RNT / 64); }
 static int odd_grid(int grid) { return (grid > 1 && grid % 2 == 0) ? grid - 1 : grid; }
 
 StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind) {
-    (void)kind;
     StripPlan p{};
+    const size_t nd = kind == STRIP_MATVEC2 ? 2 : 1;   // vectors dotted with each column
     const int vec = dtype == 0 ? 2 : (dtype == 1 ? 4 : 8);
     p.lpr = kLpr;
     p.sw = kLpr * vec;
@@ -569,7 +627,7 @@ StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind) {
         if (grid > kStripMaxGrid) grid = kStripMaxGrid;
         p.grid = odd_grid(grid < 1 ? 1 : grid);
         const int nw = kRrNt / 64;
-        p.lds = 8 * ((size_t)rg * K + 2 * (size_t)nw * p.sw) + 8 * 2 * (size_t)rg * K;
+        p.lds = 8 * nd * ((size_t)rg * K + 2 * (size_t)nw * p.sw) + 8 * 2 * (size_t)rg * K;
         if (p.lds > 160 * 1024) { p.nt = -1; return p; }
         return p;
     }
@@ -585,7 +643,7 @@ StripPlan strip_plan(int dtype, int m, int64_t n, int num_cu, int kind) {
     const int rg = p.nt / kLpr;
     const int nw = p.nt / 64;
     const size_t acc = 8;   // sized for FP64 accumulation (enough for FP32 too)
-    p.lds = acc * ((size_t)rg * p.rpt + 2 * (size_t)nw * p.sw);
+    p.lds = acc * nd * ((size_t)rg * p.rpt + 2 * (size_t)nw * p.sw);
     if (p.rpt > 16) p.lds += 8 * 2 * (size_t)p.rpt * (rg + 8);   // QL row sums (up to 2 accumulators)
     return p;
 }
@@ -596,12 +654,13 @@ hipError_t launch_strip_pass(const StripCall& c, const StripPlan& p, hipStream_t
         case STRIP_MATVEC: return dispatch_type<OpMatvec>(c, p, st);
         case STRIP_RESID: return dispatch_type<OpResid>(c, p, st);
         case STRIP_DIR: return dispatch_type<OpDir>(c, p, st);
+        case STRIP_MATVEC2: return dispatch_type<OpMatvec2>(c, p, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_strip_rowsum(const StripCall& c, const StripPlan& p, hipStream_t st) {
-    const int nacc = c.kind == STRIP_RESID ? 2 : 1;
+    const int nacc = strip_nacc(c.kind);
     const int ncr = c.kind == STRIP_RESID ? 1 : 0;
     hipLaunchKernelGGL(k_rowsum, dim3(rowsum_blocks(c.m)), dim3(RNT), 0, st, c, p.grid, nacc, ncr);
     return hipGetLastError();

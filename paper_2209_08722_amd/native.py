@@ -28,7 +28,7 @@ IPM_ERR_NOMEM = -6
 IPM_F64, IPM_F32, IPM_BF16 = 0, 1, 2
 IPM_DENSE_ROWMAJOR, IPM_CSR = 0, 1
 IPM_KERNEL_MATVEC, IPM_KERNEL_SKETCH, IPM_KERNEL_GRAM, IPM_KERNEL_MATVEC32, IPM_KERNEL_RESID64 = 0, 1, 2, 3, 4
-IPM_KERNEL_STREAM_READ, IPM_KERNEL_STREAM_COPY = 5, 6
+IPM_KERNEL_STREAM_READ, IPM_KERNEL_STREAM_COPY, IPM_KERNEL_WARM = 5, 6, 7
 IPM_PLAIN, IPM_MIXED, IPM_MIXED_F32ACC = 0, 1, 2
 IPM_WARM_NONE, IPM_WARM_PREV, IPM_WARM_GIVEN = 0, 1, 2
 

@@ -284,6 +284,52 @@ def test_step_two_candidates_matches_oracle(ctx, precision):
         assert np.linalg.norm(g - o) <= 1e-9 * np.linalg.norm(o)
 
 
+# (m, n, storage, layout): every strip-pass instance family the paired product of the two
+# candidates runs on (256-thread blocks; 512 threads with 12 and 32 rows per thread, the last
+# one per storage type) and the sparse column/row passes; n leaves a ragged last strip
+_PAIR_CASES = [(40, 1500, "f64", "dense"), (300, 5003, "f32", "dense"), (700, 4001, "bf16", "dense"),
+               (2000, 20011, "f64", "dense"), (2000, 20011, "f32", "dense"), (2000, 12007, "bf16", "dense"),
+               (200, 6000, "f64", "csr")]
+
+
+@pytest.mark.parametrize("m,n,storage,layout", _PAIR_CASES, ids=[f"{c[3]}_{c[0]}x{c[1]}_{c[2]}" for c in _PAIR_CASES])
+def test_step_two_generic_candidates_match_oracle(ctx, m, n, storage, layout):
+    """Two generic candidates (a perturbed Newton solution and a random vector): the GPU computes
+    both products M v_k in one paired pass over A; its step (CG from the M-norm-optimal
+    combination, then the update) matches the oracle's, whose products are two plain matvecs."""
+    if layout == "csr":
+        lp = lpgen.sparse_lp(m, n, 0.02, seed=13, storage=storage)
+    else:
+        lp = lpgen.dense_lp(m, n, seed=13, storage=storage)
+    prob = P.Problem.from_lp(lp, dtype=tdtype(storage))
+    w = 4 * m
+    oprm = oipm.Params(w=w, s=2, seed=5)
+    gprm = P.Params(w=w, s=2, seed=5, warm_start=P.IPM_WARM_GIVEN)
+    st = oipm.initial_state(lp.A, lp.b, lp.c)
+    for _ in range(4):
+        st, _ = oipm.step(lp.A, lp.b, lp.c, st, oprm, "sketch")
+    d2 = st.x / st.s
+    _, rd = oipm.residuals(lp.A, lp.b, lp.c, st.x, st.y, st.s)
+    p = oipm.rhs_p(lp.A, lp.b, st.x, st.s, rd, oprm.sigma, float(st.x @ st.s) / lp.n)
+    Mm = oipm.normal_matrix(lp.A, d2)
+    xs = np.linalg.solve(Mm, p)
+    rng = np.random.default_rng(3)
+    v1 = xs + 0.3 * np.linalg.norm(xs) / np.sqrt(m) * rng.standard_normal(m)
+    v2 = rng.standard_normal(m)
+    cands = np.stack([v1, v2])
+    gst = P.State(dev(st.x), dev(st.y), dev(st.s), st.k, st.mu0, st.r0norm)
+    ginfo = P.ipm_step_warm(ctx, prob, gst, gprm, dev(cands))
+    new, oinfo = oipm.step(lp.A, lp.b, lp.c, st, oprm, "sketch", dy0=cands.T.copy(), keep=True)
+    print(f"\n{layout} {m}x{n} {storage}: CG GPU {ginfo['pcg_iters']} oracle {oinfo.pcg_iters}, "
+          f"warm kept GPU {ginfo['warm_used']} oracle {int(oinfo.extra['pcg'].warm_used)}")
+    assert ginfo["warm_used"] == 1 and oinfo.extra["pcg"].warm_used
+    assert ginfo["pcg_iters"] == oinfo.pcg_iters
+    assert ginfo["alpha"] == pytest.approx(oinfo.alpha, rel=1e-10, abs=1e-12)
+    for name in ("x", "y", "s"):
+        g, o = host(getattr(gst, name)), getattr(new, name)
+        assert np.linalg.norm(g - o) <= 1e-9 * np.linalg.norm(o), name
+
+
 def test_warm_given_needs_dy0(ctx):
     lp = lpgen.dense_lp(10, 100, seed=1)
     prob = P.Problem.from_lp(lp)

@@ -198,9 +198,13 @@ def test_learned_warm_start_gain(ctx):
         cold_it += sum(i["pcg_iters"] for i in cold.infos)
         learn_it += sum(i["pcg_iters"] for i in lrn.infos)
         prev_it += sum(i["pcg_iters"] for i in prev.infos)
+    # the gain against both baselines is reported; only the one against the zero start is
+    # asserted: on this family the previous direction alone already captures most of the next one
+    # and the network's share beyond it is small (either sign at this training size)
     print(f"\nlearned warm start: {data.X.shape[0]} samples, train loss {l0:.3f} -> {hist[-1]:.3f}, "
           f"held-out loss {h0:.3f} -> {h1:.3f}; held-out CG iterations: zero start {cold_it}, "
           f"previous dy {prev_it}, network {learn_it} "
-          f"({100.0 * (cold_it - learn_it) / cold_it:.1f}% fewer than zero start)")
+          f"({100.0 * (cold_it - learn_it) / cold_it:.1f}% fewer than zero start, "
+          f"{100.0 * (prev_it - learn_it) / prev_it:+.1f}% against the previous-dy start)")
     assert hist[-1] < l0
     assert learn_it < cold_it
