@@ -189,6 +189,8 @@ def illcond_lp(m: int, n: int, seed: int = 0, matrix_seed: int = 1000,
 WORKLOADS = {
     "dense_50x2000": dict(kind="dense", m=50, n=2000, storage="f64", w=200, s=1, seeds=[0]),
     "dense_500x100000": dict(kind="dense", m=500, n=100_000, storage="f64", w=2000, s=2, seeds=[0, 1, 2, 3, 4]),
+    # the same generator with A rounded to BF16 (the mixed forms' accuracy on a dense workload)
+    "dense_500x100000_bf16": dict(kind="dense", m=500, n=100_000, storage="bf16", w=2000, s=2, seeds=[0]),
     "csr_1000x1000000": dict(kind="csr", m=1000, n=1_000_000, storage="bf16", w=4000, s=2, seeds=[0],
                              density=1e-3),
     "illcond_2000x200000": dict(kind="illcond", m=2000, n=200_000, storage="f32", w=8000, s=2,

@@ -28,7 +28,8 @@ from oracle import ipm as oipm  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_optima.json")
 
-CASES = [("dense_500x100000", s) for s in range(5)] + [("csr_1000x1000000", 0), ("csr_5000x2000000", 0)]
+CASES = ([("dense_500x100000", s) for s in range(5)] + [("dense_500x100000_bf16", 0)]
+         + [("csr_1000x1000000", 0), ("csr_5000x2000000", 0)])
 
 
 def fingerprint(lp) -> dict:
