@@ -680,6 +680,9 @@ def main() -> int:
     ap.add_argument("--learned-protocol", default="", choices=["", "illcond_2000x200000", "dense_2000x2000000"],
                     help="only run the learned warm start's train / held-out protocol on this family "
                          "(--protocol-train seeds for training, the next --protocol-test held out)")
+    ap.add_argument("--ipm-steps", default="", metavar="WORKLOAD:FORM:K",
+                    help="only run K IPM steps of a named seeded workload (lpgen.WORKLOADS, built on the host; "
+                         "FORM plain, mixed or f32acc), for kernel profiling of the sparse passes")
     ap.add_argument("--protocol-train", type=int, default=64)
     ap.add_argument("--protocol-test", type=int, default=16)
     ap.add_argument("--epochs", type=int, default=100)
@@ -720,6 +723,24 @@ def main() -> int:
         return kernel_only(args)
     import lpgen
     import paper_2209_08722_amd as P
+    if args.ipm_steps:
+        name, form, ks = args.ipm_steps.split(":")
+        lp = lpgen.workload(name)
+        tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[lp.storage]
+        prob = P.Problem.from_lp(lp, dtype=tdt)
+        prec = {"plain": P.IPM_PLAIN, "mixed": P.IPM_MIXED, "f32acc": P.IPM_MIXED_F32ACC}[form]
+        ctx = P.Context(0)
+        prm = P.Params(w=lp.meta["w"], s=lp.meta["s"], seed=0, precision=prec)
+        st = P.State.initial(lp.m, lp.n)
+        for k in range(int(ks)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = P.ipm_step(ctx, prob, st, prm)
+            torch.cuda.synchronize()
+            log(f"{name} {form} step {k}: {1e3 * (time.perf_counter() - t0):.2f} ms, CG {info['pcg_iters']}, "
+                f"relgap {info['relgap']:.2e}")
+        ctx.close()
+        return 0
     if args.learned_protocol:
         ctx = P.Context(0)
         res = learned_protocol(P, ctx, args.learned_protocol, args.protocol_train, args.protocol_test, args.epochs)

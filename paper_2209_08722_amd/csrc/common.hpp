@@ -44,12 +44,18 @@ struct HashKeys {
     double scale;      // 1 / sqrt(s)
 };
 
-// Bucket and sign of copy r of row j of W.
-__device__ __forceinline__ void w_entry(const HashKeys& hk, int r, uint64_t j, int& bucket, double& sign) {
-    const uint64_t h = mix64(hk.key[r] + (j + 1ull) * kPhi);
+// Bucket and sign of copy r of row j of W, from zj = (j + 1) * kPhi (mod 2^64), which a loop
+// over j can advance by additions.
+__device__ __forceinline__ void w_entry_z(const HashKeys& hk, int r, uint64_t zj, int& bucket, double& sign) {
+    const uint64_t h = mix64(hk.key[r] + zj);
     const uint64_t hi = h >> 32;
     bucket = r * hk.blk + (int)((hi * (uint64_t)hk.blk) >> 32);
     sign = (h & 1ull) ? -1.0 : 1.0;
+}
+
+// Bucket and sign of copy r of row j of W.
+__device__ __forceinline__ void w_entry(const HashKeys& hk, int r, uint64_t j, int& bucket, double& sign) {
+    w_entry_z(hk, r, (j + 1ull) * kPhi, bucket, sign);
 }
 
 // ---- reductions -----------------------------------------------------------------------------

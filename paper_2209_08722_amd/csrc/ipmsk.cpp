@@ -23,7 +23,8 @@ namespace {
 enum WsId {
     W_PART = 0, W_COLPART, W_RED, W_D2, W_RD, W_DS, W_DX, W_RP, W_P, W_DY, W_RHAT, W_G1, W_G2, W_U, W_B,
     W_L, W_X, W_XT, W_T, W_SCAL, W_PCG_VEC, W_PCG_RHO, W_PCG_CD, W_PCG_CI, W_STATUS, W_PART3, W_PARTMIN,
-    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_MLPF, W_MLPD, W_MLPI, W_WQ, W_COEF, W_GU, W_STREAM, W_COUNT
+    W_INFO, W_GPART, W_SQ, W_REF, W_WARM, W_PREV, W_BF, W_MLPF, W_MLPD, W_MLPI, W_WQ, W_COEF, W_GU, W_STREAM, W_SKTAB,
+    W_COUNT
 };
 
 struct TimedPair {
@@ -265,8 +266,14 @@ int do_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* dvals, int is_d2,
             HIPCHK(launch_fill_i32(reinterpret_cast<int*>(B), (int64_t)m * w, 0, ctx->stream));
         }
     }
+    double* dsc = nullptr;
+    if (sp.table) {
+        // d_j / sqrt(s) once per call
+        CHK(ws(ctx, W_SKTAB, (size_t)A->n, &dsc));
+        HIPCHK(launch_sketch_prep(A->n, dvals, is_d2, hk.scale, dsc, ctx->stream));
+    }
     Timer t(ctx, IPM_KERNEL_SKETCH);
-    HIPCHK(launch_sketch(A->dtype, A->val, m, A->n, A->ld, dvals, is_d2, hk, w, out_f64, B, sp, ctx->stream));
+    HIPCHK(launch_sketch(A->dtype, A->val, m, A->n, A->ld, dvals, is_d2, hk, w, out_f64, B, sp, dsc, ctx->stream));
     t.stop();
     return IPM_OK;
 }

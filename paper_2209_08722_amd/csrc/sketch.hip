@@ -8,7 +8,9 @@
 // type of B (FP64 LDS atomics measured several times faster than FP32 ones on gfx950 for this
 // random scatter). When one block covers all columns of its rows the bucket array is stored to B
 // (converted to B's type); otherwise blocks add their arrays into B with global atomics. W is
-// never stored: the hash is recomputed wherever W is applied.
+// never stored: the hash is recomputed wherever W is applied. A sketch whose blocks hold one or
+// two rows (a wide bucket array) first forms d_j / sqrt(s) once per call (k_sketch_prep), so that
+// the square root is not taken again for every row.
 #include "kernels.hpp"
 
 namespace ipmsk {
@@ -25,10 +27,24 @@ constexpr int SUNROLL = 4;    // columns per thread per pass (independent loads 
 template <int R>
 constexpr int sketch_unroll() { return R >= 8 ? 1 : (R >= 4 ? 2 : 4); }
 
-template <typename T, typename BT, int R>
+// d_j / sqrt(s) for every column, once per call, for the sketch with one or two rows per block
+// (which would otherwise take the square root of d2_j for every row).
+__global__ __launch_bounds__(256) void k_sketch_prep(int64_t n, const double* __restrict__ dv, int d_is_d2,
+                                                     double scale, double* __restrict__ dsc) {
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+        const double dd = dv[j];
+        dsc[j] = (d_is_d2 ? sqrt(dd) : dd) * scale;
+    }
+}
+
+// DSC: d_j / sqrt(s) read from k_sketch_prep's vector; sign * (d_j / sqrt(s)) equals
+// (sign * d_j) / sqrt(s) exactly, so B is the same either way. A thread's columns advance by
+// fixed strides, so (j + 1) kPhi of the hash advances by additions.
+template <typename T, typename BT, int R, bool DSC>
 __global__ __launch_bounds__(SNT) __attribute__((amdgpu_waves_per_eu(8))) void k_sketch_lds(const T* __restrict__ A, int m, int64_t n, int64_t ld,
                                                     const double* __restrict__ dv, int d_is_d2, HashKeys hk, int w,
-                                                    int64_t cpc, BT* __restrict__ B, int atomic) {
+                                                    int64_t cpc, BT* __restrict__ B, int atomic,
+                                                    const double* __restrict__ dsc) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* bk = reinterpret_cast<double*>(smem_raw);   // [R][w]
     const int tid = threadIdx.x;
@@ -39,15 +55,20 @@ __global__ __launch_bounds__(SNT) __attribute__((amdgpu_waves_per_eu(8))) void k
     __syncthreads();
     const int s = hk.s;
     constexpr int U = sketch_unroll<R>();
-    for (int64_t jj = jb + tid; jj < je; jj += (int64_t)SNT * U) {
+    uint64_t zj0 = ((uint64_t)(jb + tid) + 1ull) * kPhi;   // (j + 1) kPhi for this pass's first column
+    for (int64_t jj = jb + tid; jj < je; jj += (int64_t)SNT * U, zj0 += (uint64_t)SNT * U * kPhi) {
         double av[U][R];
         double dj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t j = jj + (int64_t)u * SNT;
             const bool ok = j < je;
-            double dd = ok ? dv[ok ? j : 0] : 0.0;
-            dj[u] = d_is_d2 ? sqrt(dd) : dd;
+            if constexpr (DSC) {
+                dj[u] = ok ? dsc[j] : 0.0;
+            } else {
+                double dd = ok ? dv[ok ? j : 0] : 0.0;
+                dj[u] = d_is_d2 ? sqrt(dd) : dd;
+            }
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 const int i = row0 + rr;
@@ -58,11 +79,12 @@ __global__ __launch_bounds__(SNT) __attribute__((amdgpu_waves_per_eu(8))) void k
         for (int u = 0; u < U; ++u) {
             const int64_t j = jj + (int64_t)u * SNT;
             if (j >= je) continue;
+            const uint64_t zj = zj0 + (uint64_t)u * SNT * kPhi;
             for (int r = 0; r < s; ++r) {
                 int bucket;
                 double sign;
-                w_entry(hk, r, (uint64_t)j, bucket, sign);
-                const double coef = sign * dj[u] * hk.scale;
+                w_entry_z(hk, r, zj, bucket, sign);
+                const double coef = DSC ? sign * dj[u] : sign * dj[u] * hk.scale;
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr) atomicAdd(&bk[rr * w + bucket], coef * av[u][rr]);
             }
@@ -124,15 +146,22 @@ __global__ __launch_bounds__(SNT) void k_sketch_range(const T* __restrict__ A, i
 
 template <typename T, typename BT, int R>
 void sketch_go(const T* A, int m, int64_t n, int64_t ld, const double* dv, int d2, const HashKeys& hk, int w,
-               BT* B, const SketchPlan& sp, hipStream_t st) {
+               BT* B, const SketchPlan& sp, const double* dsc, hipStream_t st) {
     const dim3 grid((m + R - 1) / R, sp.chunks);
-    IPM_LAUNCH((k_sketch_lds<T, BT, R>), grid, dim3(SNT), sp.lds, st, A, m, n, ld, dv, d2, hk, w,
-               sp.cols_per_chunk, B, sp.atomic ? 1 : 0);
+    if constexpr (R <= 2) {
+        if (sp.table) {
+            IPM_LAUNCH((k_sketch_lds<T, BT, R, true>), grid, dim3(SNT), sp.lds, st, A, m, n, ld, dv, d2, hk, w,
+                       sp.cols_per_chunk, B, sp.atomic ? 1 : 0, dsc);
+            return;
+        }
+    }
+    IPM_LAUNCH((k_sketch_lds<T, BT, R, false>), grid, dim3(SNT), sp.lds, st, A, m, n, ld, dv, d2, hk, w,
+               sp.cols_per_chunk, B, sp.atomic ? 1 : 0, nullptr);
 }
 
 template <typename T, typename BT>
 hipError_t sketch_type(const void* Av, int m, int64_t n, int64_t ld, const double* dv, int d2, const HashKeys& hk,
-                       int w, void* Bv, const SketchPlan& sp, hipStream_t st) {
+                       int w, void* Bv, const SketchPlan& sp, const double* dsc, hipStream_t st) {
     const T* A = reinterpret_cast<const T*>(Av);
     BT* B = reinterpret_cast<BT*>(Bv);
     if (sp.global_only) {
@@ -143,10 +172,10 @@ hipError_t sketch_type(const void* Av, int m, int64_t n, int64_t ld, const doubl
         return hipGetLastError();
     }
     switch (sp.rows_per_block) {
-        case 1: sketch_go<T, BT, 1>(A, m, n, ld, dv, d2, hk, w, B, sp, st); break;
-        case 2: sketch_go<T, BT, 2>(A, m, n, ld, dv, d2, hk, w, B, sp, st); break;
-        case 4: sketch_go<T, BT, 4>(A, m, n, ld, dv, d2, hk, w, B, sp, st); break;
-        case 8: sketch_go<T, BT, 8>(A, m, n, ld, dv, d2, hk, w, B, sp, st); break;
+        case 1: sketch_go<T, BT, 1>(A, m, n, ld, dv, d2, hk, w, B, sp, dsc, st); break;
+        case 2: sketch_go<T, BT, 2>(A, m, n, ld, dv, d2, hk, w, B, sp, dsc, st); break;
+        case 4: sketch_go<T, BT, 4>(A, m, n, ld, dv, d2, hk, w, B, sp, dsc, st); break;
+        case 8: sketch_go<T, BT, 8>(A, m, n, ld, dv, d2, hk, w, B, sp, dsc, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -230,6 +259,8 @@ SketchPlan sketch_plan(int m, int64_t n, int w, int out_f64, int num_cu) {
     }
     sp.rows_per_block = R;
     sp.lds = (size_t)R * w * esz;
+    // one or two rows per block: sqrt(d2_j) would be taken again for every row
+    sp.table = R <= 2;
     // Blocks resident at once: two per CU when two bucket arrays fit in LDS (the kernel is held to
     // eight waves per SIMD), else one. With the column range split into c chunks the grid runs in
     // ceil(row_blocks c / slots) rounds; per row a block streams n / c columns and clears, then
@@ -252,20 +283,27 @@ SketchPlan sketch_plan(int m, int64_t n, int w, int out_f64, int num_cu) {
     return sp;
 }
 
+hipError_t launch_sketch_prep(int64_t n, const double* dvals, int dvals_are_d2, double scale, double* dsc,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_sketch_prep, dim3(pointwise_blocks(n)), dim3(256), 0, st, n, dvals, dvals_are_d2, scale, dsc);
+    return hipGetLastError();
+}
+
 hipError_t launch_sketch(int dtype, const void* A, int m, int64_t n, int64_t ld, const double* dvals,
                          int dvals_are_d2, const HashKeys& hk, int w, int out_f64, void* B, const SketchPlan& sp,
-                         hipStream_t st) {
+                         const double* dsc, hipStream_t st) {
+    if (sp.table && dsc == nullptr) return hipErrorInvalidValue;
     if (out_f64) {
         switch (dtype) {
-            case 0: return sketch_type<double, double>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
-            case 1: return sketch_type<float, double>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
-            case 2: return sketch_type<bf16_t, double>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
+            case 0: return sketch_type<double, double>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, dsc, st);
+            case 1: return sketch_type<float, double>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, dsc, st);
+            case 2: return sketch_type<bf16_t, double>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, dsc, st);
         }
     } else {
         switch (dtype) {
-            case 0: return sketch_type<double, float>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
-            case 1: return sketch_type<float, float>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
-            case 2: return sketch_type<bf16_t, float>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, st);
+            case 0: return sketch_type<double, float>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, dsc, st);
+            case 1: return sketch_type<float, float>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, dsc, st);
+            case 2: return sketch_type<bf16_t, float>(A, m, n, ld, dvals, dvals_are_d2, hk, w, B, sp, dsc, st);
         }
     }
     return hipErrorInvalidValue;
