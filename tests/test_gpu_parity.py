@@ -105,6 +105,20 @@ def test_sketch_parity(ctx, m, n, w, s, seed, k):
     assert np.all(np.abs(B - ref) <= 32 * np.finfo(float).eps * np.sqrt(n) * bound + 1e-300)
 
 
+@pytest.mark.parametrize("m,n,w,s", [(37, 30011, 9000, 2), (10, 20011, 12000, 3), (9, 30001, 16000, 2),
+                                     (2000, 20011, 16000, 2)])
+def test_sketch_bf16_one_row_blocks(ctx, m, n, w, s):
+    """BF16 A whose w buckets fill a block's LDS (one row per block, d / sqrt(s) from the per-call
+    vector): column chunks added atomically at small m, one pass over the columns at m = 2000."""
+    A = lpgen.bf16_round(rand_lp_matrix(m, n, 31))
+    d = np.exp(np.random.default_rng(5).uniform(-2, 2, n))
+    B = host(P.ipm_sketch(ctx, P.Matrix.from_numpy(A, dtype=torch.bfloat16), dev(d), 6, 3, w, s))
+    ref = osk.sketch_ADW(A, d, w, s, 6, 3)
+    W = osk.sketch_matrix(n, w, s, 6, 3)
+    bound = np.asarray((abs(W).T @ (np.abs(A) * d).T).T)
+    assert np.all(np.abs(B - ref) <= 32 * np.finfo(float).eps * np.sqrt(n) * bound + 1e-300)
+
+
 @pytest.mark.parametrize("m,n,w,s", [(40, 3000, 160, 2), (130, 7001, 520, 2), (9, 4000, 50000, 2)])
 def test_sketch_fp32_output(ctx, m, n, w, s):
     """FP32 B: accumulated in FP64, stored rounded to FP32 (w = 50000 takes the bucket-range path)."""
