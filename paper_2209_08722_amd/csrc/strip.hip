@@ -23,6 +23,8 @@
 // matvec A D^2 A^T [v0 v1] (the warm start's two candidate products) reads A once for both.
 #include "strip_ops.hpp"
 
+#include <type_traits>
+
 namespace ipmsk {
 
 namespace {
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(RNT) void k_rowsum(StripCall a, int G, int nacc, in
     }
 }
 
-template <typename T, typename ACC, int NT, int RPT, int LPR, bool QL, class Op>
+template <typename T, typename ACC, int NT, int RPT, int LPR, bool QL, class Op, bool RL = false>
 __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
     static_assert(LPR == 4 || LPR == 8 || LPR == 16 || LPR == 32 || LPR == 64, "LPR");
     constexpr int VEC = Elem<T>::VEC;
@@ -183,13 +185,13 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
         for (int k = 0; k < (QL ? 1 : RPT); ++k) q[aa][k] = (ACC)0;
     double cr[NCR > 0 ? NCR : 1] = {0.0};
 
-    // ROLL (the CG matvec with many rows per thread, one block per CU, so no other block's loads
-    // cover this one's compute phases): the next strip's rows are loaded into the registers of
-    // this strip's rows as soon as the accumulation phase has used them, so the next strip
-    // streams in during this strip's accumulation and the next strip's column dots. Whole strips
-    // are read with buffer loads (load_group_row); the host keeps each row group's byte offsets
-    // below 2^32.
-    constexpr bool ROLL = QL && RS && Op::PF && ND == 1;
+    // ROLL (the CG matvec): the next strip's rows are loaded into the registers of this strip's
+    // rows as soon as the accumulation phase has used them, so the next strip streams in during
+    // this strip's accumulation and the next strip's column dots. Whole strips are read with
+    // buffer loads (load_group_row), whose byte offsets within a row group must stay below 2^32:
+    // the host guarantees it for the many-rows instances (QL) and selects RL (the same for the
+    // per-thread row sums, FP64 storage) only where it holds.
+    constexpr bool ROLL = (QL ? RS : RL) && Op::PF && ND == 1;
     const int64_t rowstride = (int64_t)RG * a.ld;
     const uint32_t lane_bytes = lane_off * (uint32_t)sizeof(T);
     const uint32_t group_bytes = (uint32_t)((int64_t)RG * a.ld * (int64_t)sizeof(T));
@@ -352,8 +354,13 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
                 }
             }
         } else {
+            // rolling form: the next whole strip's row k is loaded as soon as row k is summed
+            const int nxt = strip + G;
+            const int64_t jn = (int64_t)nxt * SW + c * VEC;
+            const bool roll_rows = ROLL && nxt < nstrips && whole(nxt);
+            const T* nbase = A + (int64_t)(roll_rows ? nxt : 0) * SW;
 #pragma unroll
-            for (int k = 0; k < RPT; ++k)
+            for (int k = 0; k < RPT; ++k) {
 #pragma unroll
                 for (int aa = 0; aa < NA; ++aa) {
                     ACC sacc = (ACC)0;
@@ -361,6 +368,20 @@ __global__ __launch_bounds__(NT) void k_strip(StripCall a, int nstrips) {
                     for (int e = 0; e < VEC; ++e) sacc += Elem<T>::template get<ACC>(av[k], e) * coef[aa][e];
                     q[aa][k] += sacc;
                 }
+                if constexpr (ROLL) {
+                    if (roll_rows) av[k] = load_group_row(nbase + (int64_t)k * rowstride, group_nrec(k), lane_bytes);
+                    if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            if constexpr (ROLL) {
+                if (nxt < nstrips) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) pfv[e] = Op::PF ? Op::pre(a, jn + e, jn + e < a.n) : 0.0;
+                    if (!roll_rows)
+                        load_segment<T, RPT, true>(A + (int64_t)nxt * SW + lane_off, A + (int64_t)nxt * SW + c * VEC,
+                                                   rowstride, g, RG, m, a.n - jn, av);
+                }
+            }
         }
         buf ^= 1;
     }
@@ -524,11 +545,28 @@ __global__ __launch_bounds__(NT) void k_strip_rr(StripCall a, int nstrips, int K
     }
 }
 
+// R <= 16 rows per thread with FP64 storage: the rolling form of the CG matvec when a row group's
+// byte offsets fit 32 bits (100 x 2*10^6 FP64: 545 -> 345 us; 300 x 400000: 191 -> 166 us; equal
+// at 500 x 100000 and at 512 threads). FP32 and BF16 storage keep the plain form: the rolling
+// form pushes their register use past two waves per SIMD.
 #define IPM_RPT_CASE(NTV, R)                                                                               \
     case R:                                                                                                \
+        if constexpr (std::is_same<T, double>::value && R <= 16 && Op::PF && Op::ND == 1) {               \
+            if (roll_fits(c, NTV)) {                                                                       \
+                IPM_LAUNCH((k_strip<T, ACC, NTV, R, kLpr, false, Op, true>), dim3(p.grid), dim3(NTV), p.lds, \
+                           st, c, p.nstrips);                                                              \
+                break;                                                                                     \
+            }                                                                                              \
+        }                                                                                                  \
         IPM_LAUNCH((k_strip<T, ACC, NTV, R, kLpr, (R > 16), Op>), dim3(p.grid), dim3(NTV), p.lds, st, c,   \
                    p.nstrips);                                                                             \
         break;
+
+// A row group's bytes (NT / lanes-per-row rows of ld elements) within 32-bit buffer offsets.
+inline bool roll_fits(const StripCall& c, int nt) {
+    const int es = c.dtype == 0 ? 8 : (c.dtype == 1 ? 4 : 2);
+    return (uint64_t)(nt / kLpr) * (uint64_t)c.ld * (uint64_t)es <= (uint64_t)UINT32_MAX;
+}
 
 template <typename T, typename ACC, class Op>
 hipError_t dispatch_nt(const StripCall& c, const StripPlan& p, hipStream_t st) {

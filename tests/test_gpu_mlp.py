@@ -185,7 +185,9 @@ def test_learned_warm_start_gain(ctx):
     l0, h0 = L.evaluate(ctx, net, data.X, data.T), L.evaluate(ctx, net, held.X, held.T)
     hist = L.train(ctx, net, data.X, data.T, epochs=100, batch=64, lr=1e-4, seed=0)
     h1 = L.evaluate(ctx, net, held.X, held.T)
-    cold_it = learn_it = prev_it = 0
+    cold_it = learn_it = prev_it = rand_it = 0
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(7)
     for lp in test_lps:
         prob = P.Problem.from_lp(lp)
         cold = P.solve(ctx, prob, params)
@@ -198,6 +200,22 @@ def test_learned_warm_start_gain(ctx):
         cold_it += sum(i["pcg_iters"] for i in cold.infos)
         learn_it += sum(i["pcg_iters"] for i in lrn.infos)
         prev_it += sum(i["pcg_iters"] for i in prev.infos)
+        # ablation: the previous direction with a random second candidate in place of the network's
+        st = P.State.initial(m, n)
+        cand = torch.empty((2, m), dtype=torch.float64, device="cuda:0")
+        have_prev = False
+        for _ in range(201):
+            if have_prev:
+                cand[1] = torch.randn(m, dtype=torch.float64, device="cuda:0", generator=g)
+                info = P.ipm_step_warm(ctx, prob, st, P.Params(w=w, s=2, seed=0, warm_start=P.IPM_WARM_GIVEN), cand)
+            else:
+                info = P.ipm_step(ctx, prob, st, params)
+            if info["rc"] == P.IPM_CONVERGED:
+                break
+            rand_it += info["pcg_iters"]
+            P.ipm_last_dy(ctx, m, out=cand[0])
+            have_prev = True
+        assert info["rc"] == P.IPM_CONVERGED
     # the gain against both baselines is reported; only the one against the zero start is
     # asserted: on this family the previous direction alone already captures most of the next one
     # and the network's share beyond it is small (either sign at this training size)
@@ -205,6 +223,7 @@ def test_learned_warm_start_gain(ctx):
           f"held-out loss {h0:.3f} -> {h1:.3f}; held-out CG iterations: zero start {cold_it}, "
           f"previous dy {prev_it}, network {learn_it} "
           f"({100.0 * (cold_it - learn_it) / cold_it:.1f}% fewer than zero start, "
-          f"{100.0 * (prev_it - learn_it) / prev_it:+.1f}% against the previous-dy start)")
+          f"{100.0 * (prev_it - learn_it) / prev_it:+.1f}% against the previous-dy start); previous dy with "
+          f"a random second candidate {rand_it}")
     assert hist[-1] < l0
     assert learn_it < cold_it
