@@ -58,7 +58,7 @@ def column_blocks(lp):
         yield j0, j1, host(lp.A[:, j0:j1].to(torch.float64))
 
 
-def test_4d_matvec_both_storages(ctx, lp):
+def test_matvec_both_storages(ctx, lp):
     rng = np.random.default_rng(1)
     d2 = np.exp(rng.uniform(-6, 6, N_))
     v = rng.standard_normal(M_)
@@ -77,7 +77,7 @@ def test_4d_matvec_both_storages(ctx, lp):
         assert np.all(np.abs(q - ref) <= 64 * EPS * (M_ + np.sqrt(N_)) * bound)
 
 
-def test_4d_sketch_sampled_rows(ctx, lp):
+def test_sketch_sampled_rows(ctx, lp):
     """B = A D W acts row by row: 24 sampled rows of the GPU's B (both storages, FP64 and FP32
     B) against the oracle's sketch of the same rows of A."""
     rng = np.random.default_rng(2)
@@ -125,7 +125,7 @@ def _check_solution(lp, res, label):
 
 
 @pytest.mark.timeout(600)
-def test_4d_plain_and_mixed_solves(ctx, lp):
+def test_plain_and_mixed_solves(ctx, lp):
     plain = P.solve(ctx, P.Problem(P.Matrix(lp.A64, N_), lp.b, lp.c), P.Params(w=W_, s=S_, seed=0))
     assert plain.converged
     op = _check_solution(lp, plain, "plain FP64")

@@ -251,7 +251,7 @@ def _lockstep(ctx, lp, oprm, gprm, steps, label=""):
     return recs, conv
 
 
-def test_step_lockstep_config0(ctx):
+def test_step_lockstep_dense_50x2000(ctx):
     """Every iteration of the 50 x 2000 workload (s = 1, w = 200) to the oracle's stop test."""
     lp = lpgen.workload("dense_50x2000")
     recs, conv = _lockstep(ctx, lp, oipm.Params(w=200, s=1, seed=0), P.Params(w=200, s=1, seed=0), steps=200,
@@ -295,7 +295,7 @@ def test_redraw_rule_matches_oracle(ctx, near):
         assert ginfo["shift"] == oinfo.extra["shift"] == 0
 
 
-def test_solve_config0_matches_oracle(ctx):
+def test_solve_dense_50x2000_matches_oracle(ctx):
     lp = lpgen.workload("dense_50x2000")
     res = P.solve(ctx, P.Problem.from_lp(lp), P.Params(w=200, s=1, seed=0))
     ores = oipm.solve(lp.A, lp.b, lp.c, oipm.Params(w=200, s=1, seed=0), "sketch")
@@ -401,30 +401,30 @@ def test_method_option_errors(ctx):
     assert ei.value.code == -1
 
 
-_CFG1 = {}
+_LP500 = {}
 
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("chunk", range(5))
-def test_config1_lockstep_every_iteration(ctx, chunk):
+def test_dense_500x100000_lockstep_every_iteration(ctx, chunk):
     """The bench workload (500 x 100000, w = 2000, s = 2, seed 0) in lock-step with the oracle,
     every iteration to the oracle's stop test: 12 steps per test, the oracle's iterate carried
     from one test to the next."""
     if chunk == 0:
         print("\ngenerating dense_500x100000 seed 0", flush=True)
-        _CFG1.clear()
-        _CFG1["lp"] = lpgen.workload("dense_500x100000", seed=0)
-        _CFG1["st"] = None
-    lp = _CFG1["lp"]
-    if _CFG1.get("converged"):
+        _LP500.clear()
+        _LP500["lp"] = lpgen.workload("dense_500x100000", seed=0)
+        _LP500["st"] = None
+    lp = _LP500["lp"]
+    if _LP500.get("converged"):
         return
     recs, st, conv = lockstep.run(P, ctx, lp.A, lp.b, lp.c, P.Problem.from_lp(lp), oipm.Params(w=2000, s=2, seed=0),
-                                  P.Params(w=2000, s=2, seed=0), 12, st=_CFG1["st"],
+                                  P.Params(w=2000, s=2, seed=0), 12, st=_LP500["st"],
                                   label=f"dense_500x100000 seed 0, steps {12 * chunk}-")
-    _CFG1["st"], _CFG1["converged"] = st, conv
+    _LP500["st"], _LP500["converged"] = st, conv
     if chunk == 4:
         assert conv, "the oracle's solve should stop within 60 iterations"
-        del _CFG1["lp"]
+        del _LP500["lp"]
 
 
 def _golden_optimum(key):
@@ -442,7 +442,7 @@ def _check_fingerprint(lp, fp):
 
 
 @pytest.mark.parametrize("seed", range(5))
-def test_config1_solve_matches_oracle(ctx, seed):
+def test_dense_500x100000_solve_matches_oracle(ctx, seed):
     """Seeds 0-4 of the 500 x 100000 workload: the GPU's plain FP64 solve against the oracle's
     direct-solver optimum (tests/golden/oracle_optima.json, written by make_oracle_optima.py from
     the oracle alone). Both objectives are upper bounds of the optimum within their own gap, so

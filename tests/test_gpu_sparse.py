@@ -224,15 +224,15 @@ def _golden(key, lp):
 
 
 @pytest.fixture(scope="module")
-def lp2():
+def lp_csr1k():
     print("\ngenerating the 1000 x 1e6 sparse LP (density 1e-3, BF16 values)", flush=True)
     lp = lpgen.workload("csr_1000x1000000")
     # the oracle's direct-solver optimum of this LP, written by tests/golden/make_oracle_optima.py
     return lp, _golden("csr_1000x1000000/0", lp)["objective"]
 
 
-def test_config2_full_size_matvec_and_sketch(ctx, lp2):
-    lp, _ = lp2
+def test_csr_1000x1000000_matvec_and_sketch(ctx, lp_csr1k):
+    lp, _ = lp_csr1k
     m, n = lp.A.shape
     rng = np.random.default_rng(8)
     d = np.exp(rng.uniform(-3, 3, n))
@@ -259,8 +259,8 @@ def _check(lp, res):
     return obj
 
 
-def test_config2_full_size_solves(ctx, lp2):
-    lp, opt = lp2
+def test_csr_1000x1000000_solves(ctx, lp_csr1k):
+    lp, opt = lp_csr1k
     prob64 = P.Problem(_smat(lp.A, "f64"), dev(lp.b), dev(lp.c))
     prob16 = P.Problem(_smat(lp.A, "bf16"), dev(lp.b), dev(lp.c))
     plain = P.solve(ctx, prob64, P.Params(w=4000, s=2, seed=0))
@@ -276,13 +276,13 @@ def test_config2_full_size_solves(ctx, lp2):
 # ------------------------------------------------------------------------- 5000 x 2e6 (Gram-dominated)
 
 @pytest.fixture(scope="module")
-def lp4s():
+def lp_csr5k():
     print("\ngenerating the 5000 x 2e6 sparse LP (density 5e-4, BF16 values)", flush=True)
     return lpgen.workload("csr_5000x2000000")
 
 
-def test_config4s_full_size_matvec_and_sketch(ctx, lp4s):
-    lp = lp4s
+def test_csr_5000x2000000_matvec_and_sketch(ctx, lp_csr5k):
+    lp = lp_csr5k
     m, n = lp.A.shape
     rng = np.random.default_rng(9)
     d = np.exp(rng.uniform(-3, 3, n))
@@ -303,8 +303,8 @@ def test_config4s_full_size_matvec_and_sketch(ctx, lp4s):
     assert np.max(np.abs(Bs - Bref)) <= 1e-12 * np.max(np.abs(Bref))
 
 
-def test_config4s_full_size_solves(ctx, lp4s):
-    lp = lp4s
+def test_csr_5000x2000000_solves(ctx, lp_csr5k):
+    lp = lp_csr5k
     prob64 = P.Problem(_smat(lp.A, "f64"), dev(lp.b), dev(lp.c))
     prob16 = P.Problem(_smat(lp.A, "bf16"), dev(lp.b), dev(lp.c))
     plain = P.solve(ctx, prob64, P.Params(w=40000, s=2, seed=0))

@@ -404,8 +404,8 @@ def test_sparse_matrix_branches_match_dense():
 
 
 def test_sparse_lp_optimum_matches_highs():
-    """Config-2-style sparse LP (uniform pattern, no empty column): the direct-solver IPM's
-    optimum equals HiGHS's."""
+    """Sparse LP like the 1000 x 10^6 workload (uniform pattern, no empty column): the
+    direct-solver IPM's optimum equals HiGHS's."""
     lp = lpgen.sparse_lp(40, 3000, 0.02, seed=6)
     assert np.all(lp.A.getnnz(axis=0) > 0)
     res = ipm.solve(lp.A, lp.b, lp.c, ipm.Params(), "exact")
@@ -524,7 +524,7 @@ def test_optimum_closed_form_square():
         assert np.allclose(res.state.x, np.linalg.solve(lp.A, lp.b), rtol=1e-6, atol=1e-6)
 
 
-def test_config0_matches_highs_and_duality_sandwich():
+def test_dense_50x2000_matches_highs_and_duality_sandwich():
     """Objective of the 50 x 2000 workload vs scipy's HiGHS; b^T y0 <= opt <= c^T x0."""
     lp = lpgen.workload("dense_50x2000")
     ref = linprog(lp.c, A_eq=lp.A, b_eq=lp.b, bounds=(0, None), method="highs")
