@@ -257,6 +257,7 @@ int do_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* dvals, int is_d2,
         return IPM_OK;
     }
     const SketchPlan sp = sketch_plan(m, A->n, w, out_f64, ctx->num_cu);
+    Timer t(ctx, IPM_KERNEL_SKETCH);
     if (sp.atomic) {
         if (out_f64) {
             HIPCHK(launch_fill(reinterpret_cast<double*>(B), (int64_t)m * w, 0.0, ctx->stream));
@@ -267,13 +268,19 @@ int do_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* dvals, int is_d2,
         }
     }
     double* dsc = nullptr;
+    uint32_t* tab = nullptr;
     if (sp.table) {
-        // d_j / sqrt(s) once per call
-        CHK(ws(ctx, W_SKTAB, (size_t)A->n, &dsc));
-        HIPCHK(launch_sketch_prep(A->n, dvals, is_d2, hk.scale, dsc, ctx->stream));
+        // d_j / sqrt(s) once per call and, where they pack into 32 bits, the columns' buckets and
+        // signs (n doubles, padded to an even count so that the n 32-bit entries after them start
+        // 16-byte aligned)
+        const bool packed = sketch_table_fits(hk);
+        const size_t npad = ((size_t)A->n + 1) & ~(size_t)1;
+        CHK(ws(ctx, W_SKTAB, npad + (packed ? ((size_t)A->n + 1) / 2 : 0), &dsc));
+        if (packed) tab = reinterpret_cast<uint32_t*>(dsc + npad);
+        HIPCHK(launch_sketch_prep(A->n, dvals, is_d2, hk.scale, dsc, hk, tab, ctx->stream));
     }
-    Timer t(ctx, IPM_KERNEL_SKETCH);
-    HIPCHK(launch_sketch(A->dtype, A->val, m, A->n, A->ld, dvals, is_d2, hk, w, out_f64, B, sp, dsc, ctx->stream));
+    HIPCHK(launch_sketch(A->dtype, A->val, m, A->n, A->ld, dvals, is_d2, hk, w, out_f64, B, sp, dsc, tab,
+                         ctx->stream));
     t.stop();
     return IPM_OK;
 }

@@ -97,14 +97,16 @@ hipError_t launch_sketch_csr(int dtype, const void* val, const int64_t* row_ptr,
 
 // ---- sketch and perturbation -----------------------------------------------------------------
 // table: the bucket kernel reads d_j / sqrt(s) from an n-vector (dsc) that launch_sketch_prep
-// fills first.
+// fills first, and, where sketch_table_fits(hk) (s <= 2, w / s <= 32768), each column's buckets
+// and signs from an n-vector of packed 32-bit entries (tab) filled by the same launch.
 struct SketchPlan { int rows_per_block; int chunks; int64_t cols_per_chunk; size_t lds; bool atomic; bool global_only; int range_width; bool table; };
 SketchPlan sketch_plan(int m, int64_t n, int w, int out_f64, int num_cu);
+bool sketch_table_fits(const HashKeys& hk);
 hipError_t launch_sketch_prep(int64_t n, const double* dvals, int dvals_are_d2, double scale, double* dsc,
-                              hipStream_t st);
+                              const HashKeys& hk, uint32_t* tab, hipStream_t st);
 hipError_t launch_sketch(int dtype, const void* A, int m, int64_t n, int64_t ld, const double* dvals,
                          int dvals_are_d2, const HashKeys& hk, int w, int out_f64, void* B,
-                         const SketchPlan& sp, const double* dsc, hipStream_t st);
+                         const SketchPlan& sp, const double* dsc, const uint32_t* tab, hipStream_t st);
 // u = B^T g (B m x w, FP64 or FP32); u is overwritten.
 hipError_t launch_btg(const void* B, int b_f64, int m, int w, const double* g, double* u, hipStream_t st);
 // dx and the sums a1 = x^T ds + s^T dx, a2 = dx^T ds, ||v||^2 as per-block partials [grid][3].

@@ -119,6 +119,32 @@ def test_sketch_bf16_one_row_blocks(ctx, m, n, w, s):
     assert np.all(np.abs(B - ref) <= 32 * np.finfo(float).eps * np.sqrt(n) * bound + 1e-300)
 
 
+@pytest.mark.parametrize("dt,ld", [("f64", 20016), ("f32", 20016), ("bf16", 20016), ("f64", 20014)])
+@pytest.mark.parametrize("m,n,w,s,out", [(9, 20011, 16000, 2, "f64"), (300, 20013, 9000, 1, "f32")])
+def test_sketch_one_row_blocks_row_strides(ctx, dt, ld, m, n, w, s, out):
+    """One row per block with the buckets and signs from the per-call packed table: the pipelined
+    four-column kernel for FP32 and BF16 A (ragged last quad of columns), the per-column kernel for
+    FP64 A (row strides of 4k and 4k + 2 elements); s = 1 and 2, column chunks added atomically
+    (m = 9) and one pass (m = 300)."""
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dt]
+    A = rand_lp_matrix(m, n, 41)
+    if dt == "bf16":
+        A = lpgen.bf16_round(A)
+    elif dt == "f32":
+        A = lpgen.f32_round(A)
+    pad = torch.full((m, ld), float("nan"), dtype=torch.float64)   # the padding is never read
+    pad[:, :n] = torch.from_numpy(A)
+    mat = P.Matrix(pad.to(tdt).to("cuda:0").contiguous(), n)
+    d = np.exp(np.random.default_rng(7).uniform(-2, 2, n))
+    odt = torch.float64 if out == "f64" else torch.float32
+    B = host(P.ipm_sketch(ctx, mat, dev(d), 9, 4, w, s, out_dtype=odt))
+    ref = osk.sketch_ADW(A, d, w, s, 9, 4)
+    W = osk.sketch_matrix(n, w, s, 9, 4)
+    bound = np.asarray((abs(W).T @ (np.abs(A) * d).T).T)
+    tol = 32 * np.finfo(float).eps * np.sqrt(n) * bound + (4 * 2.0 ** -24 * bound if out == "f32" else 0)
+    assert np.all(np.abs(B - ref) <= tol + 1e-300)
+
+
 @pytest.mark.parametrize("m,n,w,s", [(40, 3000, 160, 2), (130, 7001, 520, 2), (9, 4000, 50000, 2)])
 def test_sketch_fp32_output(ctx, m, n, w, s):
     """FP32 B: accumulated in FP64, stored rounded to FP32 (w = 50000 takes the bucket-range path)."""
