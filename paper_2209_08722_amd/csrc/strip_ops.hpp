@@ -18,10 +18,10 @@ struct OpMatvec {
     static constexpr int ND = 1, NACC = 1, NCR = 0;
     static constexpr bool PF = true;
     struct S {};
-    __device__ static S init(const StripCall&) { return {}; }
-    __device__ static double pre(const StripCall& a, int64_t j, bool valid) { return valid ? a.d2[j] : 0.0; }
+    __device__ __forceinline__ static S init(const StripCall&) { return {}; }
+    __device__ __forceinline__ static double pre(const StripCall& a, int64_t j, bool valid) { return valid ? a.d2[j] : 0.0; }
     template <typename ACC>
-    __device__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool, const ACC* dot,
+    __device__ __forceinline__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool, const ACC* dot,
                                   ACC* coef, double*, double pf) {
         coef[0] = valid ? (ACC)pf * dot[0] : (ACC)0;
     }
@@ -31,10 +31,10 @@ struct OpMatvec2 {
     static constexpr int ND = 2, NACC = 2, NCR = 0;
     static constexpr bool PF = true;
     struct S {};
-    __device__ static S init(const StripCall&) { return {}; }
-    __device__ static double pre(const StripCall& a, int64_t j, bool valid) { return valid ? a.d2[j] : 0.0; }
+    __device__ __forceinline__ static S init(const StripCall&) { return {}; }
+    __device__ __forceinline__ static double pre(const StripCall& a, int64_t j, bool valid) { return valid ? a.d2[j] : 0.0; }
     template <typename ACC>
-    __device__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool, const ACC* dot,
+    __device__ __forceinline__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool, const ACC* dot,
                                   ACC* coef, double*, double pf) {
         coef[0] = valid ? (ACC)pf * dot[0] : (ACC)0;
         coef[1] = valid ? (ACC)pf * dot[1] : (ACC)0;
@@ -43,12 +43,12 @@ struct OpMatvec2 {
 
 struct OpResid {
     static constexpr bool PF = false;
-    __device__ static double pre(const StripCall&, int64_t, bool) { return 0.0; }
+    __device__ __forceinline__ static double pre(const StripCall&, int64_t, bool) { return 0.0; }
     static constexpr int ND = 1, NACC = 2, NCR = 1;
     struct S { double smu; };
-    __device__ static S init(const StripCall& a) { return S{a.scal[SC_SMU]}; }
+    __device__ __forceinline__ static S init(const StripCall& a) { return S{a.scal[SC_SMU]}; }
     template <typename ACC>
-    __device__ static void column(const StripCall& a, const S& st, int64_t j, bool valid, bool writer,
+    __device__ __forceinline__ static void column(const StripCall& a, const S& st, int64_t j, bool valid, bool writer,
                                   const ACC* dot, ACC* coef, double* cr, double) {
         if (!valid) { coef[0] = coef[1] = (ACC)0; return; }
         const double sj = a.s[j];
@@ -61,12 +61,12 @@ struct OpResid {
 
 struct OpDir {
     static constexpr bool PF = false;
-    __device__ static double pre(const StripCall&, int64_t, bool) { return 0.0; }
+    __device__ __forceinline__ static double pre(const StripCall&, int64_t, bool) { return 0.0; }
     static constexpr int ND = 1, NACC = 1, NCR = 0;
     struct S {};
-    __device__ static S init(const StripCall&) { return {}; }
+    __device__ __forceinline__ static S init(const StripCall&) { return {}; }
     template <typename ACC>
-    __device__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool writer,
+    __device__ __forceinline__ static void column(const StripCall& a, const S&, int64_t j, bool valid, bool writer,
                                   const ACC* dot, ACC* coef, double*, double) {
         if (!valid) { coef[0] = (ACC)0; return; }
         const double t = (double)dot[0];
