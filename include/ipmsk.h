@@ -225,6 +225,9 @@ void ipm_params_default(ipm_params* p);
  * 2014). k is the IPM iteration (W is redrawn every iteration, Algorithm 3 step 2).
  *   A    dense m x n, any dtype;  d [device] n doubles (the diagonal of D)
  *   B    [device] m x w row-major, out_dtype IPM_F64 or IPM_F32; overwritten.
+ * The buckets accumulate in FP64 whatever out_dtype. A dense A whose w FP64 buckets exceed 64 KB
+ * (one or two rows per block) first tabulates d_j / sqrt(s) and, for s <= 2, each column's
+ * buckets and signs in the context workspace (8 n + 4 n bytes, grown on demand).
  * Errors: IPM_ERR_ARG if w < 1, s < 1, s > 8, s does not divide w, or pointers are null. */
 int ipm_sketch(ipm_ctx* ctx, const ipm_matrix* A, const double* d, uint64_t seed, int64_t k,
                int32_t w, int32_t s, int32_t out_dtype, void* B);
