@@ -863,7 +863,8 @@ def main() -> int:
         esz_low = 2 if forms == "dense_2000x2000000" else 4
         if cnt:
             out["roofline_mixed_matvec"] = roofline_record(
-                ms, cnt, f["m"] * f["n"] * esz_low + f["n"] * 8, probe["read_gbps"], None,
+                ms, cnt, f["m"] * f["n"] * esz_low + f["n"] * 8, probe["read_gbps"],
+                traffic_record(f"{forms}_bf16") if esz_low == 2 else None,
                 f"CG matvec pass of the mixed form, {'BF16' if esz_low == 2 else 'FP32'} storage, FP64 "
                 f"accumulation (k_strip OpMatvec)", probe_desc)
         out["headline_comparison"] = {
