@@ -257,20 +257,26 @@ __device__ __forceinline__ double quad_bcast(double v, int k) {
 // The block is padded to 64 x 64 with the identity (the factor and inverse of diag(A, I) are
 // diag(L, I) and diag(L^-1, I)), so no step tests bounds. Eight waves, four threads per row:
 // thread (i, q) of waves 0-3 keeps entries 16q..16q+15 of row i of the matrix in registers, thread
-// (t, q) of waves 4-7 entries 16q..16q+15 of column t of the inverse. Step c of the right-looking
-// factorization reads column c as the owners (quarter c/16) published it before the barrier:
-// entry c is the pivot a_cc, entries below it the updated a_jc, entries above it zero. With
-// g = 1/sqrt(a_cc), the row thread takes its own a_ic from the owner lane of its quad (DPP) and
-// updates a_ij -= (a_ic g^2) a_jc for its 16 columns (the zero entries leave finished columns
-// unchanged; the pivot column itself is then overwritten by l_ic = a_ic g), and the owners of
-// column c+1 publish it for the next step. The inverse threads do the matching step of the
-// column-oriented forward substitution L x = e_t: x_c = y_c g, then y_r -= (x_c g) a_rc. One
-// barrier per step; each thread's 16 reads of the column are independent, so they are all in
-// flight together. A pivot that is not positive is recorded in *status (smallest index wins) and
-// replaced by 1 so the remaining work stays finite.
+// (t, q) of waves 4-7 entries 16q..16q+15 of column t of the inverse. Step p of the right-looking
+// factorization eliminates the two columns c = 2p and c + 1 at once. Before its barrier the owners
+// (quarter c/16) published column c as updated by the columns before it (colA: the pivot a_cc,
+// the a_jc below it, zeros above) and column c + 1 as updated by the columns before c (colB: zeros
+// at rows <= c). Every thread forms the two pivots from them: g_a = 1/sqrt(a_cc),
+// l1 = l_{c+1,c} = a_{c+1,c} g_a, a' = a_{c+1,c+1} - l1^2, g_b = 1/sqrt(a'). The two rank-1 updates
+// a_ij -= l_ic l_jc + l_{i,c+1} l_{j,c+1}, with l_jc = colA[j] g_a and
+// l_{j,c+1} = (colB[j] - l_jc l1) g_b, are one pair of FMAs per entry:
+// a_ij -= colA[j] s1 + colB[j] s2, s1 = g_a (l_ic - l_{i,c+1} l1 g_b), s2 = l_{i,c+1} g_b, where
+// the row thread takes its own a_ic and a_{i,c+1} from the owner lane of its quad (DPP). Entries
+// j < c are unchanged (both columns are zero there); entries c and c + 1, where the pair of FMAs
+// is not the update, are then overwritten by l_ic and l_{i,c+1}. The inverse threads do the
+// matching two steps of the forward substitution L x = e_t: x_c = y_c g_a,
+// x_{c+1} = (y_{c+1} - x_c l1) g_b, then y_r -= colA[r] s1 + colB[r] s2 with x in place of l.
+// One barrier per two columns; each thread's reads of the two columns are independent, so they
+// are all in flight together. A pivot that is not positive is recorded in *status (smallest
+// index wins) and replaced by 1 so the remaining work stays finite.
 __global__ __launch_bounds__(512) void k_potrf_diag(double* __restrict__ Lw, int64_t ld, int k0, int kb,
                                                     double* __restrict__ X, int64_t ldx, int* __restrict__ status) {
-    __shared__ __align__(16) double colb[2][64];
+    __shared__ __align__(16) double colb[2][2][64];   // [buffer][colA, colB][row]
     const int tid = threadIdx.x;
     const bool fac = tid < 256;
     const int u = tid & 255;
@@ -284,36 +290,60 @@ __global__ __launch_bounds__(512) void k_potrf_diag(double* __restrict__ Lw, int
         if (fac && row < kb && j < kb && j <= row) v = Lw[(int64_t)(k0 + row) * ld + k0 + j];
         z[k] = v;
     }
-    if (fac && q == 0) colb[0][row] = z[0];
+    if (fac && q == 0) {
+        colb[0][0][row] = z[0];
+        colb[0][1][row] = row > 0 ? z[1] : 0.0;
+    }
     __syncthreads();
     int bad = INT_MAX;
 #pragma unroll
-    for (int c = 0; c < 64; ++c) {
-        const double* cb = colb[c & 1];
-        double piv = cb[c];
-        if (!(piv > 0.0)) {
+    for (int c = 0; c < 64; c += 2) {
+        const double* ca = colb[(c >> 1) & 1][0];
+        const double* cbv = colb[(c >> 1) & 1][1];
+        double pa = ca[c];
+        if (!(pa > 0.0)) {
             bad = min(bad, k0 + c);
-            piv = 1.0;
+            pa = 1.0;
         }
-        const double g = rsqrt(piv);
-        double cv[16];
+        const double ga = rsqrt(pa);
+        const double l1 = ca[c + 1] * ga;
+        double pb = fma(-l1, l1, cbv[c + 1]);
+        if (!(pb > 0.0)) {
+            bad = min(bad, k0 + c + 1);
+            pb = 1.0;
+        }
+        const double gb = rsqrt(pb);
+        double va[16], vb[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) cv[k] = cb[16 * q + k];
+        for (int k = 0; k < 16; ++k) {
+            va[k] = ca[16 * q + k];
+            vb[k] = cbv[16 * q + k];
+        }
         const int oq = c >> 4, ok = c & 15;
-        const double own = quad_bcast(z[ok], oq);
+        const double own0 = quad_bcast(z[ok], oq);
+        const double own1 = quad_bcast(z[ok + 1], oq);
+        double l0, lb;
         if (fac) {
-            const double l = (row == c) ? piv * g : own * g;   // l_ic (l_cc on the diagonal)
-            const double sc = l * g;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) z[k] = fma(-sc, cv[k], z[k]);
-            if (q == oq) z[ok] = l;
-            if (c + 1 < 64 && q == ((c + 1) >> 4)) colb[(c + 1) & 1][row] = row > c ? z[(c + 1) & 15] : 0.0;
+            l0 = (row == c) ? pa * ga : own0 * ga;                         // l_ic (l_cc on the diagonal)
+            lb = (row == c + 1) ? pb * gb : fma(-l0, l1, own1) * gb;     // l_{i,c+1}
         } else {
-            const double x = own * g;   // x_c = y_c / l_cc
-            const double sc = x * g;
+            l0 = own0 * ga;                                                // x_c
+            lb = fma(-l0, l1, own1) * gb;                                  // x_{c+1}
+        }
+        const double s2 = lb * gb;
+        const double s1 = ga * fma(-lb * l1, gb, l0);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) z[k] = fma(-sc, cv[k], z[k]);
-            if (q == oq) z[ok] = x;
+        for (int k = 0; k < 16; ++k) z[k] = fma(-s1, va[k], fma(-s2, vb[k], z[k]));
+        if (q == oq) {
+            z[ok] = l0;
+            z[ok + 1] = lb;
+        }
+        if (fac && c + 2 < 64 && q == ((c + 2) >> 4)) {
+            const int nk = (c + 2) & 15;
+            double* na = colb[((c >> 1) + 1) & 1][0];
+            double* nb = colb[((c >> 1) + 1) & 1][1];
+            na[row] = row > c + 1 ? z[nk] : 0.0;
+            nb[row] = row > c + 2 ? z[nk + 1] : 0.0;
         }
         __syncthreads();
     }
