@@ -196,13 +196,24 @@ def test_gpu_preconditioned_spectrum_lemma_cond3(ctx, seed):
     assert np.allclose(ev, evo, rtol=1e-9, atol=0)
 
 
-def test_precond_factor_reports_bad_pivot(ctx):
+@pytest.mark.parametrize("r", [16, 17, 70])
+def test_precond_factor_reports_bad_pivot(ctx, r):
+    """A zero row of B makes pivot r of Q = B B^T exactly zero: IPM_ERR_NOT_SPD with bad_pivot = r
+    (the diagonal blocks eliminate two columns per step: r even is a step's first pivot, r odd
+    its second; r = 70 lies in the second 64-column block)."""
+    import ctypes
     rng = np.random.default_rng(0)
     B = rng.standard_normal((80, 160))
-    B[17] = 0.0
+    B[r] = 0.0
     with pytest.raises(P.IpmError) as ei:
         P.ipm_precond_factor(ctx, dev(B))
     assert ei.value.code == -3
+    Bd = dev(B)
+    Linv = torch.empty((80, 80), dtype=torch.float64, device="cuda:0")
+    bad = ctypes.c_int64(-2)
+    rc = ctx.lib.ipm_precond_factor(ctx.h, 80, 160, P.IPM_F64, ctypes.c_void_p(Bd.data_ptr()), None,
+                                    ctypes.c_void_p(Linv.data_ptr()), ctypes.byref(bad))
+    assert rc == -3 and bad.value == r
 
 
 # ------------------------------------------------------------------------- PCG
