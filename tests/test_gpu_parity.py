@@ -120,12 +120,13 @@ def test_sketch_bf16_one_row_blocks(ctx, m, n, w, s):
 
 
 @pytest.mark.parametrize("dt,ld", [("f64", 20016), ("f32", 20016), ("bf16", 20016), ("f64", 20014)])
-@pytest.mark.parametrize("m,n,w,s,out", [(9, 20011, 16000, 2, "f64"), (300, 20013, 9000, 1, "f32")])
+@pytest.mark.parametrize("m,n,w,s,out", [(9, 20011, 16000, 2, "f64"), (300, 20013, 9000, 1, "f32"),
+                                         (3, 5, 9000, 2, "f64")])
 def test_sketch_one_row_blocks_row_strides(ctx, dt, ld, m, n, w, s, out):
     """One row per block with the buckets and signs from the per-call packed table: the pipelined
     four-column kernel for FP32 and BF16 A (ragged last quad of columns), the per-column kernel for
     FP64 A (row strides of 4k and 4k + 2 elements); s = 1 and 2, column chunks added atomically
-    (m = 9) and one pass (m = 300)."""
+    (m = 9) and one pass (m = 300); five columns (one ragged quad, most lanes without a column)."""
     tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dt]
     A = rand_lp_matrix(m, n, 41)
     if dt == "bf16":
