@@ -6,8 +6,8 @@
 // [0, 1); the entry is sqrt(-2 ln u1) cos(2 pi u2) / sqrt(w) (Box-Muller).
 //
 // The sketch is a dense contraction over n, so it runs on the FP64 MFMA units: 256 x 128 output
-// tiles (8 waves of 64 x 64), K slabs of 16 columns of A (scaled by d while staged) and the
-// matching 16 rows of W generated into LDS by the block itself, split-K over gridDim.z with
+// tiles (8 waves of 64 x 64), K slabs of 16 columns of A and the matching 16 rows of W
+// generated into LDS by the block itself and scaled by d (B = A (D W)), split-K over gridDim.z with
 // atomic accumulation into an FP64 B that the caller cleared. Generating W (two SplitMix64
 // outputs, a log, a square root and a cosine in FP64 per entry) costs about as much as the MFMA
 // work it feeds, so the tile is tall: each generated entry is used by 256 rows of A (128-row
@@ -53,6 +53,8 @@ __global__ __launch_bounds__(GNT, 1) void k_sketch_gauss(int m, int64_t n, int w
     const int sr = tid >> 1, sh = (tid & 1) * 8;          // A slab: row (of 256), first of 8 columns
     const int wk = tid >> 5, wn = (tid & 31) * 4;         // W slab: row (of 16), first of 4 columns
     double pa[8], pw[4];
+    // D scales the rows of W (B = A (D W)): one d_j per W row of the slab, where scaling A would
+    // take a load and a square root for every element of every row tile
     auto stage = [&](int64_t k0) {
         const int gr = tm + sr;
         const bool rowok = gr < m;
@@ -60,18 +62,19 @@ __global__ __launch_bounds__(GNT, 1) void k_sketch_gauss(int m, int64_t n, int w
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t j = k0 + sh + q;
-            double v = 0.0;
-            if (rowok && j < kend) {
-                const double dd = dv[j];
-                v = (double)Elem<T>::load1(arow + j) * (d_is_d2 ? sqrt(dd) : dd);
-            }
-            pa[q] = v;
+            pa[q] = (rowok && j < kend) ? (double)Elem<T>::load1(arow + j) : 0.0;
         }
         const int64_t j = k0 + wk;
+        double dj = 0.0;
+        if (j < kend) {
+            const double dd = dv[j];
+            dj = d_is_d2 ? sqrt(dd) : dd;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int c = tn + wn + q;
-            pw[q] = (j < kend && c < w) ? gauss_entry(key, (uint64_t)j * (uint64_t)w + (uint64_t)c, inv_sqrt_w) : 0.0;
+            pw[q] = (j < kend && c < w) ? gauss_entry(key, (uint64_t)j * (uint64_t)w + (uint64_t)c, inv_sqrt_w) * dj
+                                        : 0.0;
         }
     };
     auto commit = [&](int bb) {
