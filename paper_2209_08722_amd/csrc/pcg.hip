@@ -51,6 +51,11 @@ __device__ __forceinline__ void preload_lower(const double* __restrict__ M, int 
     }
 }
 
+// Beyond the preloaded entries a lane loads RU entries of its row together (predicated), then
+// adds them in ascending order: the same sums as one entry at a time, with one round trip per
+// RU entries instead of one per entry (rows of thousands of entries at m = 2000 and 5000).
+constexpr int RU = 8;
+
 __device__ __forceinline__ double finish_lower(const double* __restrict__ M, int m, int row, const double* xs,
                                                int lane, const double* mv) {
     double acc = 0.0;
@@ -60,7 +65,19 @@ __device__ __forceinline__ double finish_lower(const double* __restrict__ M, int
         if (l <= row) acc += mv[u] * xs[l];
     }
     const double* mr = M + (int64_t)row * m;
-    for (int l = lane + 64 * PRE; l <= row; l += 64) acc += mr[l] * xs[l];
+    for (int l0 = lane + 64 * PRE; l0 <= row; l0 += 64 * RU) {
+        double v[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int l = l0 + 64 * u;
+            v[u] = l <= row ? mr[l] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int l = l0 + 64 * u;
+            if (l <= row) acc += v[u] * xs[l];
+        }
+    }
     return wave_sum(acc);
 }
 
@@ -82,7 +99,19 @@ __device__ __forceinline__ double finish_upper(const double* __restrict__ M, int
         if (l < m) acc += mv[u] * xs[l];
     }
     const double* mr = M + (int64_t)row * m;
-    for (int l = row + lane + 64 * PRE; l < m; l += 64) acc += mr[l] * xs[l];
+    for (int l0 = row + lane + 64 * PRE; l0 < m; l0 += 64 * RU) {
+        double v[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int l = l0 + 64 * u;
+            v[u] = l < m ? mr[l] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int l = l0 + 64 * u;
+            if (l < m) acc += v[u] * xs[l];
+        }
+    }
     return wave_sum(acc);
 }
 
@@ -194,7 +223,18 @@ __global__ __launch_bounds__(GNT) void k_pcg_gemv1(PcgBufs b, int j) {
     double mv[PRE];
     preload_lower(b.X, m, row0, lane, mv);
     double dqp = 0.0;
-    for (int l = tid; l < m; l += GNT) dqp += b.dv[l] * b.q[l];
+    for (int l0 = tid; l0 < m; l0 += GNT * RU) {   // loads RU at a time, added in ascending order
+        double dvv[RU], qv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int l = l0 + GNT * u;
+            dvv[u] = l < m ? b.dv[l] : 0.0;
+            qv[u] = l < m ? b.q[l] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (l0 + GNT * u < m) dqp += dvv[u] * qv[u];
+    }
     const double dq = block_sum(dqp, sh);
     if (!(dq > 0.0)) {
         if (blockIdx.x == 0 && tid == 0) {
@@ -207,12 +247,36 @@ __global__ __launch_bounds__(GNT) void k_pcg_gemv1(PcgBufs b, int j) {
     const double alpha = b.cd[PD_RHO0 + par] / dq;
     if (b.ahist != nullptr && blockIdx.x == 0 && tid == 0) b.ahist[j] = alpha;
     const double* __restrict__ rin = b.r[par];
-    for (int l = tid; l < m; l += GNT) {
-        const double rn = rin[l] - alpha * b.q[l];
-        xs[l] = rn;
+    constexpr int VU = 4;
+    for (int l0 = tid; l0 < m; l0 += GNT * VU) {
+        double rv[VU], qv[VU];
+#pragma unroll
+        for (int u = 0; u < VU; ++u) {
+            const int l = l0 + GNT * u;
+            rv[u] = l < m ? rin[l] : 0.0;
+            qv[u] = l < m ? b.q[l] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < VU; ++u) {
+            const int l = l0 + GNT * u;
+            if (l < m) xs[l] = rv[u] - alpha * qv[u];
+        }
         if (blockIdx.x == 0) {
-            b.r[par ^ 1][l] = rn;
-            b.dy[par ^ 1][l] = b.dy[par][l] + alpha * b.dv[l];
+            double yv[VU], dvv[VU];
+#pragma unroll
+            for (int u = 0; u < VU; ++u) {
+                const int l = l0 + GNT * u;
+                yv[u] = l < m ? b.dy[par][l] : 0.0;
+                dvv[u] = l < m ? b.dv[l] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < VU; ++u) {
+                const int l = l0 + GNT * u;
+                if (l < m) {
+                    b.r[par ^ 1][l] = rv[u] - alpha * qv[u];
+                    b.dy[par ^ 1][l] = yv[u] + alpha * dvv[u];
+                }
+            }
         }
     }
     __syncthreads();
@@ -237,7 +301,14 @@ __global__ __launch_bounds__(GNT) void k_pcg_gemv2(PcgBufs b, int j) {
     preload_upper(b.XT, m, row0, lane, mv);
     const double rho_new = sum_partials(b.rho_part, b.n_rho, 1, sh);
     const double beta = rho_new / b.cd[PD_RHO0 + par];
-    for (int l = tid; l < m; l += GNT) xs[l] = b.wv[l];
+    for (int l0 = tid; l0 < m; l0 += GNT * RU) {
+        double wv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) wv[u] = l0 + GNT * u < m ? b.wv[l0 + GNT * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (l0 + GNT * u < m) xs[l0 + GNT * u] = wv[u];
+    }
     __syncthreads();
     for (int row = row0; row < m; row += gridDim.x * GNW) {
         if (row != row0) preload_upper(b.XT, m, row, lane, mv);
