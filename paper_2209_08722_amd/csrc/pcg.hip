@@ -22,11 +22,20 @@ namespace {
 constexpr int GNT = 256;       // threads per GEMV block
 constexpr int GNW = GNT / 64;  // rows in flight per block (one wave per row)
 
+// Row dots of the triangular factors: a lane loads eight of its entries together (predicated),
+// then adds them in ascending order, the same sum as one entry at a time.
 __device__ __forceinline__ double row_dot_lower(const double* __restrict__ M, int m, int row, const double* xs,
                                                 int lane) {
     const double* mr = M + (int64_t)row * m;
     double acc = 0.0;
-    for (int l = lane; l <= row; l += 64) acc += mr[l] * xs[l];
+    for (int l0 = lane; l0 <= row; l0 += 64 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = l0 + 64 * u <= row ? mr[l0 + 64 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (l0 + 64 * u <= row) acc += v[u] * xs[l0 + 64 * u];
+    }
     return wave_sum(acc);
 }
 
@@ -34,7 +43,14 @@ __device__ __forceinline__ double row_dot_upper(const double* __restrict__ M, in
                                                 int lane) {
     const double* mr = M + (int64_t)row * m;
     double acc = 0.0;
-    for (int l = row + lane; l < m; l += 64) acc += mr[l] * xs[l];
+    for (int l0 = row + lane; l0 < m; l0 += 64 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = l0 + 64 * u < m ? mr[l0 + 64 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (l0 + 64 * u < m) acc += v[u] * xs[l0 + 64 * u];
+    }
     return wave_sum(acc);
 }
 
